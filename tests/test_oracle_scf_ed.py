@@ -1,0 +1,49 @@
+"""Pins of the whole oracle SCF against exact diagonalisation and MP2.
+
+Second Born solved self-consistently is exact through second order in the
+interaction: E_2B(lam) - E_ED(lam) = O(lam^3), so doubling lam multiplies the
+difference by ~8. The same holds for HF + MP2, which checks the ED and MP2
+code independently of the Green's-function path."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fedvr, hf as H, scf as SC, ed as ED
+
+
+def test_ed_noninteracting_and_variational():
+    st = fedvr.Setup(W.he_1d(half_width=6.0, n_e=3, n_g=4).with_(ee_scale=0.0))
+    e = np.linalg.eigvalsh(st.h)
+    assert abs(ED.ed_ground_energy(st.T, st.v, st.V) - 2 * e[0]) < 1e-12
+    st = fedvr.Setup(W.config_he())
+    E0, _, _ = ED.rhf_zero_temperature(st.h, st.V, 1)
+    assert ED.ed_ground_energy(st.T, st.v, st.V) < E0
+
+
+def test_he_config_scf():
+    """The 19-function He system: E_HF > E_2B > E_ED, N stays 2, jump condition."""
+    sysd = W.config_he()
+    r = SC.scf(sysd, tol=1e-8)
+    st = r.setup
+    Eed = ED.ed_ground_energy(st.T, st.v, st.V)
+    assert r.converged and r.iters < 100
+    assert r.hf.E > r.E > Eed
+    assert abs(r.N - 2.0) < 1e-3
+    assert np.max(np.abs(r.G[0] + r.G[-1] + np.eye(st.h.shape[0]))) < 1e-12
+    frac = (r.E - r.hf.E) / (Eed - r.hf.E)
+    assert 0.5 < frac < 0.8
+
+
+@pytest.mark.slow
+def test_second_order_exactness_against_ed():
+    d2b, dmp2 = [], []
+    for lam in (0.1, 0.2):
+        sysd = W.he_1d(half_width=6.0, n_e=3, n_g=4, beta=40.0, M=1024).with_(ee_scale=lam)
+        r = SC.scf(sysd, tol=1e-13, alpha=0.7)
+        st = r.setup
+        Eed = ED.ed_ground_energy(st.T, st.v, st.V)
+        E0, eps0, C0 = ED.rhf_zero_temperature(st.h, st.V, 1)
+        d2b.append(r.E - Eed)
+        dmp2.append(E0 + ED.mp2_closed_shell(eps0, C0, st.V, 1) - Eed)
+    assert 7.0 < d2b[1] / d2b[0] < 9.5
+    assert 7.0 < dmp2[1] / dmp2[0] < 9.5
