@@ -1,0 +1,261 @@
+/*
+ * negf.h -- C ABI of the MI355X FE-DVR second-Born ground-state library.
+ *
+ * The method: Balzer, Bauch, Bonitz, "Finite elements and the discrete
+ * variable representation in nonequilibrium Green's function calculations.
+ * Atomic and molecular models". Sec. 2.1-2.2 build the FE-DVR basis and the
+ * one- and two-body matrices; Sec. 2.3 gives the HF and second-Born
+ * self-energies (Eqs. sigmahf, sigma2ndb), the HF Green's function (Eqs.
+ * hamhf, hfgf) and the Matsubara Dyson equation (Eq. deq).
+ *
+ * Conventions shared by every call
+ *   - Status: every call returns NEGF_OK (0) or a negative NEGF_E* code; on
+ *     error negf_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread). No C++ exception crosses the ABI.
+ *   - Arguments are validated on the host before any device work; an invalid
+ *     argument returns NEGF_EINVAL and launches nothing.
+ *   - Ownership: the caller owns every buffer passed in. The library never
+ *     frees caller memory. Scratch memory belongs to a negf_ctx and lives until
+ *     negf_ctx_destroy.
+ *   - Device pointers ("dev") must be device memory of the context's GPU; host
+ *     pointers ("host") ordinary host memory.
+ *   - stream: a hipStream_t (NULL = the default stream). Calls that only write
+ *     device outputs are stream-ordered and asynchronous; calls that return
+ *     host scalars synchronise the stream before returning.
+ *   - Layouts are row-major. An n_b x n_b matrix A has A[i*n_b + j]. A
+ *     tau-resolved tensor is [n_tau][n_b][n_b]; slot 0 holds the value at
+ *     tau = 0^+ and slot n_tau-1 the value at tau = beta^-.
+ *   - One spin channel is stored; sigma (1 or 2) is the spin degeneracy.
+ *     G(tau) = -<T psi(tau) psi^dagger(0)> on [0, beta]; the density matrix is
+ *     rho = -G(beta^-) and the particle number N = -sigma Tr G(beta^-).
+ *   - Tau grids are symmetric under tau -> beta - tau (slot q pairs with slot
+ *     n_tau-1-q); the uniform grid and the power mesh both are.
+ *   - The second-Born kernels use G_q^T = G_q: every slice of G must be
+ *     symmetric (the Dyson iteration keeps it so).
+ */
+#ifndef NEGF_H
+#define NEGF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define NEGF_OK        0
+#define NEGF_EINVAL   -1   /* invalid argument (checked before any device work) */
+#define NEGF_ENODEV   -2   /* no usable GPU / wrong device */
+#define NEGF_EHIP     -3   /* a HIP runtime call failed */
+#define NEGF_ENAN     -4   /* NaN/Inf appeared in an energy or particle number */
+#define NEGF_ENOCONV  -5   /* iteration limit reached before the tolerance */
+#define NEGF_ENOMEM   -6   /* device allocation failed */
+
+/* ------------------------------------------------------------------ enums */
+#define NEGF_F64   0       /* storage and arithmetic in float64 */
+#define NEGF_F32   1       /* storage and arithmetic in float32 */
+#define NEGF_BF16  2       /* float32 storage; dense products on bf16 MFMA, float32 accumulation */
+
+#define NEGF_TAU_UNIFORM 0 /* M intervals, M+1 points */
+#define NEGF_TAU_POWER   1 /* power mesh, 2 u p + 1 points */
+
+#define NEGF_CONV_AUTO   0 /* Fourier route on uniform grids, direct quadrature otherwise */
+#define NEGF_CONV_FFT    1 /* antiperiodic DFT route; uniform grids only */
+#define NEGF_CONV_DIRECT 2 /* direct split-trapezoid quadrature (any grid) */
+
+const char* negf_last_error(void);
+int negf_version(void);
+
+/* ------------------------------------------------------------------ context */
+typedef struct negf_ctx negf_ctx;
+
+/* Create a context bound to GPU `device` (scratch buffers, Fourier tables).
+ * *out receives the handle. Errors: NEGF_EINVAL (out NULL), NEGF_ENODEV. */
+int negf_ctx_create(int device, negf_ctx** out);
+/* Release the context's device scratch. NULL is accepted. */
+int negf_ctx_destroy(negf_ctx* ctx);
+/* Bytes of device scratch currently held by the context. */
+int negf_ctx_scratch_bytes(const negf_ctx* ctx, size_t* bytes);
+
+/* ------------------------------------------------------------------ grid */
+/* Basis size of n_e elements with n_g basis functions each: n_b = n_e n_g - 1
+ * (Sec. 2.1, Eq. basisdim). n_g is the number of generalized Gauss-Lobatto
+ * points per element minus one. Errors: NEGF_EINVAL if n_e < 1 or n_g < 2. */
+int negf_fedvr_size(int n_e, int n_g, int* n_b);
+
+typedef struct {
+    int n_e;                 /* number of finite elements */
+    int n_g;                 /* basis functions per element (GLL points - 1) */
+    const double* bounds;    /* host, n_e+1 strictly increasing element boundaries */
+} negf_grid_t;
+
+typedef struct {
+    int n_c;                 /* number of nuclei (0..64) */
+    const double* X;         /* host, n_c positions */
+    const double* Z;         /* host, n_c charges */
+    double soft;             /* v(x) = -sum Z_c / sqrt((x - X_c)^2 + soft) */
+    double ee_soft;          /* V(x,x') = ee_scale / sqrt((x - x')^2 + ee_soft) */
+    double ee_scale;
+} negf_potential_t;
+
+/* FE-DVR setup (Sec. 2.1-2.2): GLL nodes and weights per element (Eqs. xim,
+ * wim), bridge/element basis with Dirichlet ends (Eq. basis), kinetic matrix
+ * (Eq. tmat), diagonal potential (Eq. vmat) and the diagonal-pair interaction
+ * kernel V_ab = u(|x_a - x_b|) (Eqs. umat1, umatred).
+ * Outputs (host, float64): x[n_b] nodes, W[n_b] summed GLL weights,
+ * T[n_b*n_b], v[n_b], V[n_b*n_b]. Any output may be NULL to skip it.
+ * Errors: NEGF_EINVAL for bad sizes, non-increasing bounds, soft <= 0. */
+int fedvr_build(const negf_grid_t* grid, const negf_potential_t* pot,
+                double* x, double* W, double* T, double* v, double* V);
+
+/* Number of stored tau points: M+1 (uniform, M >= 2 even) or 2 u p + 1
+ * (power mesh, u >= 4, p >= 1). */
+int negf_tau_count(int kind, int M, int u, int p, int* n_tau);
+/* Tau points (host, n_tau doubles). Uniform: beta q / M. Power mesh (Sec. 3.1,
+ * the cited power mesh): breakpoints 0, beta/2^p, ..., beta/2, each interval
+ * split into u equal steps, mirrored about beta/2. Both grids are built as
+ * their first half plus its mirror beta - tau, so they are exactly symmetric. */
+int negf_tau_grid(int kind, double beta, int M, int u, int p, double* tau);
+
+/* ------------------------------------------------------------------ HF */
+/* Self-consistent Hartree-Fock ground state on the GPU in float64 (Sec. 2.3,
+ * Eqs. sigmahf, hamhf): F = h + Sigma^HF[rho], F = C diag(eps) C^T by a
+ * cyclic Jacobi eigensolver, mu by bisection so that sum_k f(eps_k - mu) =
+ * n_elec/sigma, rho = C f C^T; repeated until |dE| < tol and
+ * max|d rho| < 10 tol, at most max_iter times. Start: rho of h = T + diag(v).
+ * Inputs (dev, float64): T[n_b*n_b], v[n_b], V[n_b*n_b].
+ * Outputs (dev, float64): eps[n_b] ascending, C[n_b*n_b] (column k is the
+ * eigenvector of eps_k), rho[n_b*n_b], Sigma0[n_b*n_b] = F - h of the last
+ * diagonalised F; (host) *mu, *E_hf = sigma(Tr[h rho] + Tr[Sigma^HF[rho] rho]/2),
+ * *iters. Synchronises the stream.
+ * Errors: NEGF_EINVAL; NEGF_ENOCONV (outputs valid, last iterate); NEGF_ENAN. */
+int negf_hf(negf_ctx* ctx, int n_b, const double* T, const double* v, const double* V,
+            double n_elec, int sigma, double beta, double tol, int max_iter,
+            double* eps, double* C, double* rho, double* Sigma0,
+            double* mu, double* E_hf, int* iters, void* stream);
+
+/* HF Green's function on the tau grid (Eq. hfgf moved to tau > 0):
+ * G0(tau_q) = -C diag((1 - f_k) e^(-tau_q xi_k)) C^T, xi = eps - mu, evaluated
+ * with non-positive exponents only.
+ * tau (host, n_tau); eps, C (dev, float64); G0 (dev, [n_tau][n_b][n_b],
+ * float64 or float32 by dtype NEGF_F64 / NEGF_F32). */
+int negf_g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau, double beta,
+                  const double* eps, const double* C, double mu, void* G0, int dtype,
+                  void* stream);
+
+/* ------------------------------------------------------------------ Sigma 2B */
+/* Second-Born correlation self-energy for every tau slice (Sec. 2.3,
+ * Eq. sigma2ndb with the interaction lines at equal times):
+ *   Sigma_c,ij(tau) = sum_kl V_ik V_jl [sigma G_ij G_kl Gb_lk - G_il Gb_lk G_kj],
+ *   Gb = G(beta - tau) = slot n_tau-1-q.
+ * The slices q and n_tau-1-q are computed together (they share their
+ * intermediate products). Cost: about n_b^4 + 10 n_b^3 flops per slice.
+ * V (dev, float64 for NEGF_F64, float32 otherwise) [n_b*n_b], symmetric.
+ * G (dev) [n_tau][n_b][n_b], every slice symmetric; Sigma_c (dev, same shape);
+ * G and Sigma_c are float64 for NEGF_F64 and float32 for NEGF_F32 / NEGF_BF16.
+ * For NEGF_BF16 each slice is scaled by a power of two before rounding to
+ * bf16 and the result unscaled, so no slice underflows before the output.
+ * Sigma_c must not alias G. Errors: NEGF_EINVAL (n_b < 1, n_tau < 2, sigma
+ * not 1 or 2, bad dtype, NULL pointers). */
+int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
+                 const void* G, void* Sigma_c, int dtype, void* stream);
+
+/* ------------------------------------------------------------------ Dyson */
+typedef struct {
+    int kind;                /* NEGF_TAU_UNIFORM or NEGF_TAU_POWER */
+    int n_tau;               /* number of points */
+    int block;               /* power mesh: u (steps per uniform block); 0 for uniform */
+    double beta;
+    const double* tau;       /* host, n_tau points as from negf_tau_grid */
+} negf_tau_grid_t;
+
+/* One step of the Matsubara Dyson equation (Sec. 2.3, Eq. deq) with linear
+ * mixing, plus the total energy of the incoming G:
+ *   rho = -G(beta^-), St = Sigma^HF[rho] - Sigma0,
+ *   I1 = St G + Q[Sigma_c, G],  I2 = Q[G0, I1],  G_new = G0 + I2,
+ *   G_out = (1 - alpha) G_in + alpha G_new, then G_out = (G_out + G_out^T)/2
+ *   slice by slice if symmetrize.
+ * Q is the split trapezoid rule: the tau-bar integral is split at tau_p and
+ * each part uses the trapezoid rule on the grid points it covers, with the
+ * antiperiodic continuation A(s - beta) = -A(s). G0 enters through its
+ * eigen-decomposition (eps, C, mu) exactly; on the power mesh Sigma_c between
+ * grid points is 4-point Lagrange-interpolated within its uniform block.
+ * conv_algo picks the route for Q[Sigma_c, G] (both give the same sums on
+ * uniform grids; NEGF_CONV_FFT needs a uniform grid with n_tau - 1 a power of two).
+ * Energy (Galitskii-Migdal, computed in float64 whatever dtype):
+ *   E = sigma(Tr[h rho] + Tr[Sigma^HF[rho] rho]/2)
+ *       - sigma/2 sum_q w_q Tr[Sigma_c(beta - tau_q) G(tau_q)],
+ *   w = trapezoid weights; N = -sigma Tr G(beta^-).
+ * Inputs (dev): h = T + diag(v), V, Sigma0, C [n_b*n_b] float64; eps [n_b]
+ * float64; G_in, Sigma_c [n_tau][n_b][n_b] in dtype (NEGF_F64 or NEGF_F32).
+ * Outputs: G_out (dev, dtype; may alias G_in); *E_out, *N_out (host; either may be
+ * NULL). Synchronises the stream when E_out or N_out is non-NULL.
+ * Errors: NEGF_EINVAL, NEGF_ENAN (E or N not finite; G_out still written). */
+int negf_dyson_step(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma,
+                    const double* h, const double* V, const double* eps, const double* C,
+                    double mu, const double* Sigma0, const void* G_in, const void* Sigma_c,
+                    double alpha, int symmetrize, int conv_algo, int dtype, void* G_out,
+                    double* E_out, double* N_out, void* stream);
+
+/* Galitskii-Migdal energy and particle number of (G, Sigma_c) alone (float64
+ * accumulation), the same formulas as in negf_dyson_step. Synchronises. */
+int negf_energy(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma,
+                const double* h, const double* V, const void* G, const void* Sigma_c,
+                int dtype, double* E_out, double* N_out, void* stream);
+
+/* ------------------------------------------------------------------ SCF */
+typedef struct {
+    negf_grid_t grid;
+    negf_potential_t pot;
+    double n_elec;           /* electrons (both spins) */
+    int sigma;               /* spin degeneracy, 1 or 2 */
+    double beta;             /* inverse temperature */
+    int tau_kind;            /* NEGF_TAU_UNIFORM / NEGF_TAU_POWER */
+    int M;                   /* uniform: intervals */
+    int u, p;                /* power mesh */
+    double e_nn;             /* constant added once to the total energy */
+} negf_system_t;
+
+typedef struct {
+    double alpha;            /* linear mixing, (0, 1] */
+    double tol;              /* stop when |E_k - E_(k-1)| < tol (Ha) */
+    int max_iter;            /* limit on Dyson steps */
+    int fixed_iters;         /* > 0: run exactly this many Dyson steps, ignore tol */
+    int dtype;               /* NEGF_F64, or NEGF_F32 / NEGF_BF16 for the mixed form */
+    int conv_algo;           /* NEGF_CONV_* */
+    int symmetrize;          /* 1: symmetrise every iterate */
+    double refine_tol;       /* mixed form: after the low-precision loop, float64
+                                steps until |dE| < refine_tol (<= 0: tol) */
+    double hf_tol;           /* HF stopping rule (<= 0: 1e-13) */
+    int hf_max_iter;         /* (<= 0: 1000) */
+} negf_opts_t;
+
+typedef struct {
+    int iter;                /* Dyson steps done before this energy */
+    int dtype;               /* arithmetic of the step that produced G_iter */
+    double E, dE, N;         /* energy of G_iter, change, particle number */
+    double ms;               /* wall time of the iteration (sigma + energy + step) */
+} negf_iter_log_t;
+
+/* Whole self-consistent second-Born ground state (Sec. 2.3): fedvr_build,
+ * negf_hf, G = G0 (or G_guess), then for k = 0, 1, ...:
+ *   Sigma_c = Sigma_2B[G_k]; E_k = E_GM[G_k]; stop if k >= 1 and
+ *   |E_k - E_(k-1)| < tol; else G_(k+1) = Dyson step of G_k.
+ * Mixed form (dtype F32/BF16): the loop runs in float32 until tol, then
+ * float64 steps continue from that G until refine_tol.
+ * G_guess (dev, float64, [n_tau][n_b][n_b], nullable) replaces G0 as the start.
+ * G_out (dev, float64, nullable) receives the final G; *E_out, *N_out, *iters
+ * (host, nullable) the final energy, particle number and number of Dyson steps
+ * (all precisions). log (host, nullable) receives up to log_cap records.
+ * HF results (host, nullable): hf_E, hf_mu.
+ * Errors: NEGF_EINVAL, NEGF_ENOCONV (outputs hold the last iterate), NEGF_ENAN,
+ * NEGF_ENOMEM. */
+int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* opts,
+             const double* G_guess, double* G_out, double* E_out, double* N_out,
+             int* iters, negf_iter_log_t* log, int log_cap, double* hf_E, double* hf_mu,
+             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEGF_H */

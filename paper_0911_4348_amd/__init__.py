@@ -1,0 +1,364 @@
+"""Python binding of the MI355X FE-DVR second-Born library (``libnegf.so``).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels (or, for the FE-DVR setup and tau grids, its host C++).
+PyTorch is used for device memory and streams. The C names and their
+documentation are in ``include/negf.h``.
+
+If the shared library has not been built, importing this module still works
+but every call raises ``RuntimeError``; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnegf.so")
+
+OK, EINVAL, ENODEV, EHIP, ENAN, ENOCONV, ENOMEM = 0, -1, -2, -3, -4, -5, -6
+F64, F32, BF16 = 0, 1, 2
+TAU_UNIFORM, TAU_POWER = 0, 1
+CONV_AUTO, CONV_FFT, CONV_DIRECT = 0, 1, 2
+
+_NAMES = {OK: "NEGF_OK", EINVAL: "NEGF_EINVAL", ENODEV: "NEGF_ENODEV", EHIP: "NEGF_EHIP",
+          ENAN: "NEGF_ENAN", ENOCONV: "NEGF_ENOCONV", ENOMEM: "NEGF_ENOMEM"}
+
+
+class NegfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ------------------------------------------------------------------ C structs
+class GridT(C.Structure):
+    _fields_ = [("n_e", C.c_int), ("n_g", C.c_int), ("bounds", C.POINTER(C.c_double))]
+
+
+class PotentialT(C.Structure):
+    _fields_ = [("n_c", C.c_int), ("X", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)),
+                ("soft", C.c_double), ("ee_soft", C.c_double), ("ee_scale", C.c_double)]
+
+
+class TauGridT(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n_tau", C.c_int), ("block", C.c_int), ("beta", C.c_double),
+                ("tau", C.POINTER(C.c_double))]
+
+
+class SystemT(C.Structure):
+    _fields_ = [("grid", GridT), ("pot", PotentialT), ("n_elec", C.c_double), ("sigma", C.c_int),
+                ("beta", C.c_double), ("tau_kind", C.c_int), ("M", C.c_int), ("u", C.c_int),
+                ("p", C.c_int), ("e_nn", C.c_double)]
+
+
+class OptsT(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("fixed_iters", C.c_int), ("dtype", C.c_int), ("conv_algo", C.c_int),
+                ("symmetrize", C.c_int), ("refine_tol", C.c_double), ("hf_tol", C.c_double),
+                ("hf_max_iter", C.c_int)]
+
+
+class IterLogT(C.Structure):
+    _fields_ = [("iter", C.c_int), ("dtype", C.c_int), ("E", C.c_double), ("dE", C.c_double),
+                ("N", C.c_double), ("ms", C.c_double)]
+
+
+# ------------------------------------------------------------------ loading
+_lib = None
+
+_VP, _DP, _IP = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+_SIGS = {
+    "negf_last_error": (C.c_char_p, []),
+    "negf_version": (C.c_int, []),
+    "negf_ctx_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+    "negf_ctx_destroy": (C.c_int, [_VP]),
+    "negf_ctx_scratch_bytes": (C.c_int, [_VP, C.POINTER(C.c_size_t)]),
+    "negf_fedvr_size": (C.c_int, [C.c_int, C.c_int, _IP]),
+    "fedvr_build": (C.c_int, [C.POINTER(GridT), C.POINTER(PotentialT), _DP, _DP, _DP, _DP, _DP]),
+    "negf_tau_count": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _IP]),
+    "negf_tau_grid": (C.c_int, [C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, _DP]),
+    "negf_hf": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_double, C.c_int, C.c_double, C.c_double,
+                          C.c_int, _VP, _VP, _VP, _VP, _DP, _DP, _IP, _VP]),
+    "negf_g0_build": (C.c_int, [_VP, C.c_int, C.c_int, _DP, C.c_double, _VP, _VP, C.c_double, _VP,
+                                C.c_int, _VP]),
+    "negf_sigma2b": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _VP]),
+    "negf_dyson_step": (C.c_int, [_VP, C.POINTER(TauGridT), C.c_int, C.c_int, _VP, _VP, _VP, _VP,
+                                  C.c_double, _VP, _VP, _VP, C.c_double, C.c_int, C.c_int, C.c_int,
+                                  _VP, _DP, _DP, _VP]),
+    "negf_energy": (C.c_int, [_VP, C.POINTER(TauGridT), C.c_int, C.c_int, _VP, _VP, _VP, _VP, C.c_int,
+                              _DP, _DP, _VP]),
+    "negf_scf": (C.c_int, [_VP, C.POINTER(SystemT), C.POINTER(OptsT), _VP, _VP, _DP, _DP, _IP,
+                           C.POINTER(IterLogT), C.c_int, _DP, _DP, _VP]),
+}
+
+
+def lib():
+    """The loaded shared library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0911_4348_amd/build.py "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise NegfError(rc, lib().negf_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+# ------------------------------------------------------------------ torch helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+_DT = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+
+
+def _tensor_dtype(dt):
+    torch = _torch()
+    return torch.float64 if _DT[dt] == F64 else torch.float32
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """A library context on one GPU (owns the device scratch)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().negf_ctx_create(device, C.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def scratch_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(lib().negf_ctx_scratch_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().negf_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ setup (host)
+def fedvr_size(n_e: int, n_g: int) -> int:
+    n = C.c_int()
+    _check(lib().negf_fedvr_size(n_e, n_g, C.byref(n)))
+    return n.value
+
+
+def _grid_pot(bounds, n_g, centres, charges, soft, ee_soft, ee_scale):
+    b = np.ascontiguousarray(bounds, dtype=np.float64)
+    X = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1)
+    Z = np.ascontiguousarray(charges, dtype=np.float64).reshape(-1)
+    g = GridT(len(b) - 1, n_g, _dptr(b))
+    p = PotentialT(len(X), _dptr(X) if len(X) else None, _dptr(Z) if len(Z) else None,
+                   soft, ee_soft, ee_scale)
+    return g, p, (b, X, Z)
+
+
+def fedvr_build(bounds, n_g, centres, charges, soft=1.0, ee_soft=1.0, ee_scale=1.0):
+    """Host FE-DVR setup; returns numpy (x, W, T, v, V)."""
+    g, p, keep = _grid_pot(bounds, n_g, centres, charges, soft, ee_soft, ee_scale)
+    n = fedvr_size(g.n_e, n_g)
+    x, W, v = np.zeros(n), np.zeros(n), np.zeros(n)
+    T, V = np.zeros((n, n)), np.zeros((n, n))
+    _check(lib().fedvr_build(C.byref(g), C.byref(p), _dptr(x), _dptr(W), _dptr(T), _dptr(v), _dptr(V)))
+    return x, W, T, v, V
+
+
+def fedvr_build_system(sysd):
+    return fedvr_build(sysd.bounds, sysd.n_g, sysd.centres, sysd.charges, sysd.soft, sysd.ee_soft,
+                       sysd.ee_scale)
+
+
+def tau_grid(kind, beta, M=0, u=0, p=0) -> np.ndarray:
+    kind = TAU_UNIFORM if kind in ("uniform", TAU_UNIFORM) else TAU_POWER
+    n = C.c_int()
+    _check(lib().negf_tau_count(kind, M, u, p, C.byref(n)))
+    t = np.zeros(n.value)
+    _check(lib().negf_tau_grid(kind, beta, M, u, p, _dptr(t)))
+    return t
+
+
+def tau_grid_system(sysd) -> np.ndarray:
+    return tau_grid(sysd.tau_kind, sysd.beta, sysd.M, sysd.u, sysd.p)
+
+
+class TauGrid:
+    """Host description of a tau grid, kept alive for the C struct."""
+
+    def __init__(self, kind, beta, tau: np.ndarray, block: int = 0):
+        self.kind = TAU_UNIFORM if kind in ("uniform", TAU_UNIFORM) else TAU_POWER
+        self.beta = float(beta)
+        self.tau = np.ascontiguousarray(tau, dtype=np.float64)
+        self.block = int(block)
+        self.struct = TauGridT(self.kind, len(self.tau), self.block, self.beta, _dptr(self.tau))
+
+    @classmethod
+    def of_system(cls, sysd):
+        return cls(sysd.tau_kind, sysd.beta, tau_grid_system(sysd),
+                   sysd.u if sysd.tau_kind == "power" else 0)
+
+
+# ------------------------------------------------------------------ device calls
+@dataclass
+class HFState:
+    eps: object
+    C: object
+    rho: object
+    Sigma0: object
+    mu: float
+    E: float
+    iters: int
+
+
+def hf(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1000, stream=None) -> HFState:
+    """negf_hf on device tensors T, v, V (float64)."""
+    torch = _torch()
+    n = v.shape[0]
+    dev = T.device
+    eps = torch.empty(n, dtype=torch.float64, device=dev)
+    Cm = torch.empty((n, n), dtype=torch.float64, device=dev)
+    rho = torch.empty((n, n), dtype=torch.float64, device=dev)
+    S0 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    mu, E, it = C.c_double(), C.c_double(), C.c_int()
+    _check(lib().negf_hf(ctx.handle, n, _dev_ptr(T), _dev_ptr(v), _dev_ptr(V), float(n_elec), int(sigma),
+                         float(beta), float(tol), int(max_iter), _dev_ptr(eps), _dev_ptr(Cm), _dev_ptr(rho),
+                         _dev_ptr(S0), C.byref(mu), C.byref(E), C.byref(it), _stream(stream)))
+    return HFState(eps, Cm, rho, S0, mu.value, E.value, it.value)
+
+
+def g0_build(ctx: Context, hfs: HFState, tau: np.ndarray, beta, dtype="f64", stream=None):
+    torch = _torch()
+    n = hfs.eps.shape[0]
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    G0 = torch.empty((len(tau), n, n), dtype=_tensor_dtype(dtype), device=hfs.eps.device)
+    _check(lib().negf_g0_build(ctx.handle, n, len(tau), _dptr(tau), float(beta), _dev_ptr(hfs.eps),
+                               _dev_ptr(hfs.C), float(hfs.mu), _dev_ptr(G0), _DT[dtype], _stream(stream)))
+    return G0
+
+
+def sigma2b(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=None):
+    """negf_sigma2b: returns Sigma_c with the shape of G."""
+    torch = _torch()
+    n_tau, n, _ = G.shape
+    if out is None:
+        out = torch.empty_like(G)
+    _check(lib().negf_sigma2b(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
+                              _DT[dtype], _stream(stream)))
+    return out
+
+
+def dyson_step(ctx: Context, tg: TauGrid, sigma, h, V, hfs: HFState, G_in, Sc, alpha, symmetrize=True,
+               conv=CONV_AUTO, dtype="f64", G_out=None, want_energy=True, stream=None):
+    """negf_dyson_step; returns (G_out, E, N) (E, N of G_in, None if not requested)."""
+    torch = _torch()
+    n = G_in.shape[1]
+    if G_out is None:
+        G_out = torch.empty_like(G_in)
+    E, N = C.c_double(), C.c_double()
+    _check(lib().negf_dyson_step(ctx.handle, C.byref(tg.struct), n, int(sigma), _dev_ptr(h), _dev_ptr(V),
+                                 _dev_ptr(hfs.eps), _dev_ptr(hfs.C), float(hfs.mu), _dev_ptr(hfs.Sigma0),
+                                 _dev_ptr(G_in), _dev_ptr(Sc), float(alpha), int(symmetrize), int(conv),
+                                 _DT[dtype], _dev_ptr(G_out), C.byref(E) if want_energy else None,
+                                 C.byref(N) if want_energy else None, _stream(stream)))
+    return G_out, (E.value if want_energy else None), (N.value if want_energy else None)
+
+
+def energy(ctx: Context, tg: TauGrid, sigma, h, V, G, Sc, dtype="f64", stream=None):
+    n = G.shape[1]
+    E, N = C.c_double(), C.c_double()
+    _check(lib().negf_energy(ctx.handle, C.byref(tg.struct), n, int(sigma), _dev_ptr(h), _dev_ptr(V),
+                             _dev_ptr(G), _dev_ptr(Sc), _DT[dtype], C.byref(E), C.byref(N), _stream(stream)))
+    return E.value, N.value
+
+
+@dataclass
+class SCFOut:
+    G: object
+    E: float
+    N: float
+    iters: int
+    hf_E: float
+    hf_mu: float
+    log: list
+    status: int
+
+
+def system_struct(sysd):
+    """Build the C negf_system_t for a workloads.System (returns struct, keep-alive)."""
+    g, p, keep = _grid_pot(sysd.bounds, sysd.n_g, sysd.centres, sysd.charges, sysd.soft, sysd.ee_soft,
+                           sysd.ee_scale)
+    kind = TAU_UNIFORM if sysd.tau_kind == "uniform" else TAU_POWER
+    s = SystemT(g, p, float(sysd.n_elec), int(sysd.sigma), float(sysd.beta), kind, int(sysd.M),
+                int(sysd.u), int(sysd.p), float(sysd.e_nn))
+    return s, keep
+
+
+def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
+        conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
+        allow_noconv=False, stream=None) -> SCFOut:
+    """negf_scf for a workloads.System."""
+    torch = _torch()
+    s, keep = system_struct(sysd)
+    o = OptsT(float(alpha), float(tol), int(max_iter), int(fixed_iters), _DT[dtype], int(conv),
+              int(symmetrize), float(refine_tol), 0.0, 0)
+    n = sysd.n_b
+    n_tau = sysd.n_tau
+    G = torch.empty((n_tau, n, n), dtype=torch.float64, device="cuda") if want_G else None
+    E, N, it, hE, hmu = C.c_double(), C.c_double(), C.c_int(), C.c_double(), C.c_double()
+    cap = max_iter + 2 if not fixed_iters else fixed_iters + 2
+    cap = max(cap, 4) + max_iter
+    logs = (IterLogT * cap)()
+    rc = lib().negf_scf(ctx.handle, C.byref(s), C.byref(o), _dev_ptr(G_guess), _dev_ptr(G), C.byref(E),
+                        C.byref(N), C.byref(it), logs, cap, C.byref(hE), C.byref(hmu), _stream(stream))
+    if rc != OK and not (allow_noconv and rc == ENOCONV):
+        _check(rc)
+    rec = [dict(iter=logs[k].iter, dtype=logs[k].dtype, E=logs[k].E, dE=logs[k].dE, N=logs[k].N,
+                ms=logs[k].ms) for k in range(cap) if k == 0 or logs[k].iter != 0]
+    rec = [r for r in rec if r["ms"] > 0]
+    return SCFOut(G, E.value, N.value, it.value, hE.value, hmu.value, rec, rc)

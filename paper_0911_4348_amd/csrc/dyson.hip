@@ -1,0 +1,677 @@
+// One step of the Matsubara Dyson equation and the Galitskii-Migdal energy
+// (paper Sec. 2.3, Eq. deq and the text after it).
+//
+//   rho = -G(beta^-),  St = Sigma^HF[rho] - Sigma0
+//   I1_p = St G_p + Q_p[Sigma_c, G],  I2_p = Q_p[G0, I1],
+//   G_out = (1 - alpha) G_in + alpha (G0 + I2),  optionally (G + G^T)/2.
+//
+// Q is the split trapezoid rule: the integral over [0, beta] is split at tau_p
+// and each part uses the trapezoid rule on the grid points it covers, with the
+// antiperiodic continuation A(s - beta) = -A(s) and one-sided values at the
+// split point.
+//
+// Q[Sigma_c, G]: on a uniform grid with M = 2^L intervals, for 0 < p < M the
+// sum is an antiperiodic circular convolution of length M (jump averages at
+// q = 0); it is computed through the DFT at the odd Matsubara frequencies:
+// real columns are packed in pairs, twisted by e^(-i pi q / M) and transformed
+// in LDS, the static term St enters as a frequency-independent addition, and
+// p = 0, M are corrected with one n_b x n_b product. Any grid (and the power
+// mesh, with 4-point Lagrange interpolation of Sigma_c inside its uniform
+// block) can use the direct double sum on the matrix cores instead.
+//
+// Q[G0, I1]: in the HF eigenbasis G0 is diagonal, G0 = -C diag(g(tau)) C^T,
+// g_k(s) = (1 - f_k) e^(-s xi_k), so each (k, column) pair needs two
+// first-order recurrences over tau, arranged so that every exponential factor
+// is <= 1 (forward decay or a prefix sum with e^(xi tau) for xi < 0, and the
+// mirror images backwards). G0 itself is added in the same pass.
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "mfma.h"
+
+namespace negf {
+namespace {
+
+inline unsigned grid_for(long total) {
+    long b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <int NT>
+__device__ double block_sum_d(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < NT / 64; ++k) s += red[k];
+        red[NT / 64] = s;
+    }
+    __syncthreads();
+    return red[NT / 64];
+}
+
+// ------------------------------------------------------------ St = Sigma^HF[-G_M] - Sigma0
+template <class T>
+__global__ void k_sigma_tilde(int n, int sigma, const double* __restrict__ V, const T* __restrict__ GM,
+                              const double* __restrict__ Sigma0, T* __restrict__ St) {
+    const long nn = (long)n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        double s = V[e] * (double)GM[e];                 // -V_ij rho_ij with rho = -G_M
+        if (i == j) {
+            double h = 0.0;
+            for (int k = 0; k < n; ++k) h -= V[(long)i * n + k] * (double)GM[(long)k * n + k];
+            s += sigma * h;
+        }
+        St[e] = (T)(s - Sigma0[e]);
+    }
+}
+
+// ------------------------------------------------------------ FFT in LDS
+__device__ __forceinline__ int bitrev(int x, int L) { return (int)(__brev((unsigned)x) >> (32 - L)); }
+
+template <class T>
+__device__ void fft_stages(T* br, T* bi, int M, int L, int CW, const T* __restrict__ tw) {
+    for (int s = 1; s <= L; ++s) {
+        const int half = 1 << (s - 1), stride = M >> s;
+        for (int b = threadIdx.x; b < (M >> 1) * CW; b += blockDim.x) {
+            const int w = b / (M >> 1), bb = b % (M >> 1);
+            const int grp = bb >> (s - 1), pos = bb & (half - 1);
+            const int i0 = w * M + grp * 2 * half + pos, i1 = i0 + half;
+            const T twr = tw[2 * pos * stride], twi = tw[2 * pos * stride + 1];
+            const T ar = br[i1], ai = bi[i1];
+            const T tr = ar * twr - ai * twi, ti = ar * twi + ai * twr;
+            const T ur = br[i0], ui = bi[i0];
+            br[i0] = ur + tr;
+            bi[i0] = ui + ti;
+            br[i1] = ur - tr;
+            bi[i1] = ui - ti;
+        }
+        __syncthreads();
+    }
+}
+
+// A_k = sum_{q<M} x^_q e^(-i pi (2k+1) q / M) for k < M/2 and every real column
+// of X [M+1][nc], with x^_0 = (X_0 - X_M)/2. Output planar [M/2][nc].
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_fwd(int nc, int M, int L, int CW, const T* __restrict__ X,
+                                                 const T* __restrict__ twist, const T* __restrict__ tw,
+                                                 T* __restrict__ Are, T* __restrict__ Aim) {
+    extern __shared__ unsigned char sm_raw[];
+    T* br = reinterpret_cast<T*>(sm_raw);
+    T* bi = br + CW * M;
+    const long c0 = (long)blockIdx.x * 2 * CW;
+    for (int idx = threadIdx.x; idx < M * CW; idx += blockDim.x) {
+        const int q = idx / CW, w = idx % CW;
+        const long c1 = c0 + 2 * w, c2 = c1 + 1;
+        T x1 = 0, x2 = 0;
+        if (q == 0) {
+            if (c1 < nc) x1 = T(0.5) * (X[c1] - X[(long)M * nc + c1]);
+            if (c2 < nc) x2 = T(0.5) * (X[c2] - X[(long)M * nc + c2]);
+        } else {
+            if (c1 < nc) x1 = X[(long)q * nc + c1];
+            if (c2 < nc) x2 = X[(long)q * nc + c2];
+        }
+        const T cr = twist[2 * q], ci = twist[2 * q + 1];
+        const int r = w * M + bitrev(q, L);
+        br[r] = x1 * cr - x2 * ci;
+        bi[r] = x1 * ci + x2 * cr;
+    }
+    __syncthreads();
+    fft_stages(br, bi, M, L, CW, tw);
+    for (int idx = threadIdx.x; idx < (M >> 1) * CW; idx += blockDim.x) {
+        const int k = idx / CW, w = idx % CW;
+        const long c1 = c0 + 2 * w, c2 = c1 + 1;
+        const T zr = br[w * M + k], zi = bi[w * M + k];
+        const T yr = br[w * M + M - 1 - k], yi = bi[w * M + M - 1 - k];
+        if (c1 < nc) {
+            Are[(long)k * nc + c1] = T(0.5) * (zr + yr);
+            Aim[(long)k * nc + c1] = T(0.5) * (zi - yi);
+        }
+        if (c2 < nc) {
+            Are[(long)k * nc + c2] = T(0.5) * (zi + yi);
+            Aim[(long)k * nc + c2] = T(-0.5) * (zr - yr);
+        }
+    }
+}
+
+// out_q = (1/M) sum_{k<M} C_k e^(i pi (2k+1) q / M), q < M, for real outputs
+// whose spectra satisfy C_(M-1-k) = conj(C_k); input planar [M/2][nc].
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_inv(int nc, int M, int L, int CW, const T* __restrict__ Cre,
+                                                 const T* __restrict__ Cim, const T* __restrict__ twist,
+                                                 const T* __restrict__ tw, T* __restrict__ out) {
+    extern __shared__ unsigned char sm_raw[];
+    T* br = reinterpret_cast<T*>(sm_raw);
+    T* bi = br + CW * M;
+    const long c0 = (long)blockIdx.x * 2 * CW;
+    for (int idx = threadIdx.x; idx < (M >> 1) * CW; idx += blockDim.x) {
+        const int k = idx / CW, w = idx % CW;
+        const long c1 = c0 + 2 * w, c2 = c1 + 1;
+        T a_r = 0, a_i = 0, b_r = 0, b_i = 0;
+        if (c1 < nc) { a_r = Cre[(long)k * nc + c1]; a_i = Cim[(long)k * nc + c1]; }
+        if (c2 < nc) { b_r = Cre[(long)k * nc + c2]; b_i = Cim[(long)k * nc + c2]; }
+        // Z_k = C1_k + i C2_k, Z_(M-1-k) = conj(C1_k) + i conj(C2_k); store conj(Z)
+        const int r0 = w * M + bitrev(k, L), r1 = w * M + bitrev(M - 1 - k, L);
+        br[r0] = a_r - b_i;
+        bi[r0] = -(a_i + b_r);
+        br[r1] = a_r + b_i;
+        bi[r1] = -(b_r - a_i);
+    }
+    __syncthreads();
+    fft_stages(br, bi, M, L, CW, tw);
+    const T sc = T(1) / T(M);
+    for (int idx = threadIdx.x; idx < M * CW; idx += blockDim.x) {
+        const int q = idx / CW, w = idx % CW;
+        const long c1 = c0 + 2 * w, c2 = c1 + 1;
+        const T yr = br[w * M + q] * sc, yi = -bi[w * M + q] * sc;
+        const T cr = twist[2 * q], ci = twist[2 * q + 1];          // e^(-i pi q/M); multiply by its conjugate
+        if (c1 < nc) out[(long)q * nc + c1] = yr * cr + yi * ci;
+        if (c2 < nc) out[(long)q * nc + c2] = yi * cr - yr * ci;
+    }
+}
+
+// A'_k = dtau A_k + St (St real, the same for every frequency)
+template <class T>
+__global__ void k_freq_prep(long nn, int nk, T dtau, const T* __restrict__ St, T* __restrict__ Are, T* __restrict__ Aim) {
+    const long tot = nn * nk;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        Are[e] = dtau * Are[e] + St[e % nn];
+        Aim[e] = dtau * Aim[e];
+    }
+}
+
+// L = St/2 - dtau/4 (Sc_0 + Sc_M), R = G_0 + G_M
+template <class T>
+__global__ void k_endpoint_prep(long nn, T dtau, const T* St, const T* Sc0, const T* ScM, const T* G0,
+                                const T* GM, T* Lm, T* Rm) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+        Lm[e] = T(0.5) * St[e] - T(0.25) * dtau * (Sc0[e] + ScM[e]);
+        Rm[e] = G0[e] + GM[e];
+    }
+}
+
+// I1_0 += E, I1_M = St R - I1_0
+template <class T>
+__global__ void k_endpoint_final(long nn, const T* E, const T* SR, T* I0, T* IM) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+        const T v = I0[e] + E[e];
+        I0[e] = v;
+        IM[e] = SR[e] - v;
+    }
+}
+
+// ------------------------------------------------------------ direct quadrature (any grid)
+struct Stencil {
+    int cnt;
+    int node[8];
+    double wt[8];
+};
+
+__device__ void interp4(const double* tau, int n_tau, int block, double s, double scale, Stencil& st) {
+    int lo = 0, hi = n_tau - 1;                    // largest a with tau[a] <= s
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tau[mid] <= s) lo = mid;
+        else hi = mid;
+    }
+    int a = tau[hi] <= s ? hi : lo;
+    if (a > n_tau - 2) a = n_tau - 2;
+    if (a < 0) a = 0;
+    const int blo = (a / block) * block;
+    const int bhi = min(blo + block, n_tau - 1);
+    int start = a - 1;
+    if (start < blo) start = blo;
+    if (start > bhi - 3) start = bhi - 3;
+    for (int m = 0; m < 4; ++m) {
+        double w = 1.0;
+        for (int j = 0; j < 4; ++j)
+            if (j != m) w *= (s - tau[start + j]) / (tau[start + m] - tau[start + j]);
+        st.node[st.cnt] = start + m;
+        st.wt[st.cnt] = scale * w;
+        ++st.cnt;
+    }
+}
+
+__device__ void make_stencil(int p, int q, int n_tau, int kind, int block, const double* tau,
+                             const double* w, Stencil& st) {
+    const int M = n_tau - 1;
+    const double beta = tau[M];
+    st.cnt = 0;
+    if (p > 0 && q <= p) {
+        const double wl = q < p ? w[q] : 0.5 * (tau[p] - tau[p - 1]);
+        if (q == p) { st.node[st.cnt] = 0; st.wt[st.cnt++] = wl; }
+        else if (kind == NEGF_TAU_UNIFORM) { st.node[st.cnt] = p - q; st.wt[st.cnt++] = wl; }
+        else interp4(tau, n_tau, block, tau[p] - tau[q], wl, st);
+    }
+    if (p < M && q >= p) {
+        const double wr = q > p ? w[q] : 0.5 * (tau[p + 1] - tau[p]);
+        if (q == p) { st.node[st.cnt] = M; st.wt[st.cnt++] = -wr; }
+        else if (kind == NEGF_TAU_UNIFORM) { st.node[st.cnt] = M + p - q; st.wt[st.cnt++] = -wr; }
+        else interp4(tau, n_tau, block, beta + tau[p] - tau[q], -wr, st);
+    }
+}
+
+// Out[p] = sum_q sum_m wt_m Sc[node_m] G[q] for one 64 x 64 output tile of slice p.
+template <class T>
+__global__ __launch_bounds__(256) void k_conv_direct(int n, int n_tau, int kind, int block,
+                                                     const double* __restrict__ tau, const double* __restrict__ w,
+                                                     const T* __restrict__ Sc, const T* __restrict__ G,
+                                                     T* __restrict__ Out) {
+    __shared__ T As[16][66];
+    __shared__ T Bs[16][66];
+    __shared__ Stencil sst;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    const int p = blockIdx.z, m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const long nn = (long)n * n;
+    typename Mma<T>::acc_t acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mma<T>::zero();
+    for (int q = 0; q < n_tau; ++q) {
+        __syncthreads();
+        if (tid == 0) make_stencil(p, q, n_tau, kind, block, tau, w, sst);
+        __syncthreads();
+        const int cnt = sst.cnt;
+        if (cnt == 0) continue;
+        const T* Gq = G + (long)q * nn;
+        for (int k0 = 0; k0 < n; k0 += 16) {
+            T ra[4], rb[4];
+            {
+                const int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
+                for (int e = 0; e < 4; ++e) {
+                    const int k = kb + e;
+                    double v = 0.0;
+                    if (m < n && k < n)
+                        for (int c = 0; c < cnt; ++c) v += sst.wt[c] * (double)Sc[(long)sst.node[c] * nn + (long)m * n + k];
+                    ra[e] = (T)v;
+                }
+                const int kk = k0 + (tid >> 4), nb = n0 + (tid & 15) * 4;
+                for (int e = 0; e < 4; ++e) {
+                    const int j = nb + e;
+                    rb[e] = (kk < n && j < n) ? Gq[(long)kk * n + j] : T(0);
+                }
+            }
+            __syncthreads();
+            for (int e = 0; e < 4; ++e) As[(tid & 3) * 4 + e][tid >> 2] = ra[e];
+            for (int e = 0; e < 4; ++e) Bs[tid >> 4][(tid & 15) * 4 + e] = rb[e];
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kk = ks * 4 + (lane >> 4);
+                T a0 = As[kk][wr * 32 + (lane & 15)], a1 = As[kk][wr * 32 + 16 + (lane & 15)];
+                T b0 = Bs[kk][wc * 32 + (lane & 15)], b1 = Bs[kk][wc * 32 + 16 + (lane & 15)];
+                acc[0][0] = Mma<T>::mma(a0, b0, acc[0][0]);
+                acc[0][1] = Mma<T>::mma(a0, b1, acc[0][1]);
+                acc[1][0] = Mma<T>::mma(a1, b0, acc[1][0]);
+                acc[1][1] = Mma<T>::mma(a1, b1, acc[1][1]);
+            }
+        }
+    }
+    for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr * 32 + mi * 16 + Mma<T>::row(lane, r);
+                const int col = n0 + wc * 32 + ni * 16 + (lane & 15);
+                if (row < n && col < n) Out[(long)p * nn + (long)row * n + col] = acc[mi][ni][r];
+            }
+}
+
+// ------------------------------------------------------------ eigenbasis recurrences
+// Ea[q][k] = e^(-a tau_q), Eb[q][k] = e^(-a (beta - tau_q)), dec[q][k] = e^(-a (tau_(q+1) - tau_q)),
+// a = |eps_k - mu|; cpre[k] = 1 / (1 + e^(-a beta)).
+__global__ void k_scan_tables(int n, int n_tau, const double* __restrict__ tau, double beta,
+                              const double* __restrict__ eps, double mu, double* Ea, double* Eb, double* dec,
+                              double* cpre) {
+    const long tot = (long)n * n_tau;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int q = (int)(e / n), k = (int)(e % n);
+        const double a = fabs(eps[k] - mu);
+        Ea[e] = exp(-a * tau[q]);
+        Eb[e] = exp(-a * (beta - tau[q]));
+        dec[e] = q + 1 < n_tau ? exp(-a * (tau[q + 1] - tau[q])) : 0.0;
+        if (q == 0) cpre[k] = 1.0 / (1.0 + exp(-a * beta));
+    }
+}
+
+// Out[p][k][j] = Q_p[-g_k, In[.][k][j]] - g_k(tau_p) C[j][k]: the eigenbasis form
+// of G0 + Q[G0, I1] before the final rotation by C.
+template <class T>
+__global__ __launch_bounds__(256) void k_eig_scan(int n, int n_tau, const T* __restrict__ In, T* __restrict__ Out,
+                                                  const double* __restrict__ w, const double* __restrict__ hL,
+                                                  const double* __restrict__ hR, const double* __restrict__ Ea,
+                                                  const double* __restrict__ Eb, const double* __restrict__ dec,
+                                                  const double* __restrict__ cpre, const double* __restrict__ eps,
+                                                  double mu, const double* __restrict__ C) {
+    const long nn = (long)n * n;
+    const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (e >= nn) return;
+    const int k = (int)(e / n), j = (int)(e % n);
+    const bool pos = eps[k] - mu >= 0.0;
+    const double c = cpre[k];
+    const int M = n_tau - 1;
+    double acc = 0.0;
+    if (pos) {
+        for (int p = 0; p <= M; ++p) {
+            const double b = (double)In[(long)p * nn + e];
+            Out[(long)p * nn + e] = (T)(c * (acc + hL[p] * b));
+            if (p < M) acc = dec[(long)p * n + k] * (acc + w[p] * b);
+        }
+    } else {
+        for (int p = 0; p <= M; ++p) {
+            const double b = (double)In[(long)p * nn + e];
+            const double ea = Ea[(long)p * n + k];
+            Out[(long)p * nn + e] = (T)(c * Eb[(long)p * n + k] * (acc + hL[p] * ea * b));
+            acc += w[p] * ea * b;
+        }
+    }
+    const double cjk = C[(long)j * n + k];
+    acc = 0.0;
+    if (pos) {
+        for (int p = M; p >= 0; --p) {
+            const double b = (double)In[(long)p * nn + e];
+            const double eb = Eb[(long)p * n + k], ea = Ea[(long)p * n + k];
+            const double R = c * ea * (acc + hR[p] * eb * b);
+            acc += w[p] * eb * b;
+            const double L = (double)Out[(long)p * nn + e];
+            Out[(long)p * nn + e] = (T)(-L + R - c * ea * cjk);
+        }
+    } else {
+        for (int p = M; p >= 0; --p) {
+            const double b = (double)In[(long)p * nn + e];
+            const double R = c * (acc + hR[p] * b);
+            if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b);
+            const double L = (double)Out[(long)p * nn + e];
+            Out[(long)p * nn + e] = (T)(-L + R - c * Eb[(long)p * n + k] * cjk);
+        }
+    }
+}
+
+template <class T>
+__global__ void k_symmetrize(int n, long nslices, T* G) {
+    const long nn = (long)n * n;
+    const long tot = nn * nslices;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const long s = e / nn, r = e % nn;
+        const int i = (int)(r / n), j = (int)(r % n);
+        if (i < j) {
+            T* g = G + s * nn;
+            const T v = T(0.5) * (g[(long)i * n + j] + g[(long)j * n + i]);
+            g[(long)i * n + j] = v;
+            g[(long)j * n + i] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ energy
+template <class T>
+__global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T* __restrict__ Sc,
+                                                       const T* __restrict__ G, double* part) {
+    __shared__ double red[256 / 64 + 1];
+    const int q = blockIdx.x;
+    const long nn = (long)n * n;
+    const T* S = Sc + (long)(n_tau - 1 - q) * nn;
+    const T* g = G + (long)q * nn;
+    double s = 0.0;
+    for (long e = threadIdx.x; e < nn; e += 256) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        s += (double)S[e] * (double)g[(long)j * n + i];
+    }
+    s = block_sum_d<256>(s, red);
+    if (threadIdx.x == 0) part[q] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_energy_final(int n, int n_tau, int sigma, const double* __restrict__ h,
+                                                      const double* __restrict__ V, const T* __restrict__ GM,
+                                                      const double* __restrict__ w, const double* __restrict__ part,
+                                                      double* out) {
+    __shared__ double red[256 / 64 + 1];
+    double ec = 0.0;
+    for (int q = threadIdx.x; q < n_tau; q += 256) ec += w[q] * part[q];
+    ec = block_sum_d<256>(ec, red);
+    const long nn = (long)n * n;
+    double e1 = 0.0, e2 = 0.0, tr = 0.0;
+    for (long e = threadIdx.x; e < nn; e += 256) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        const double rij = -(double)GM[e], rji = -(double)GM[(long)j * n + i];
+        const double rii = -(double)GM[(long)i * n + i], rjj = -(double)GM[(long)j * n + j];
+        e1 += h[e] * rji;
+        e2 += sigma * rii * V[e] * rjj - V[e] * rij * rji;
+        if (i == j) tr += rii;
+    }
+    e1 = block_sum_d<256>(e1, red);
+    e2 = block_sum_d<256>(e2, red);
+    tr = block_sum_d<256>(tr, red);
+    if (threadIdx.x == 0) {
+        out[0] = sigma * (e1 + 0.5 * e2) - 0.5 * sigma * ec;
+        out[1] = sigma * tr;
+    }
+}
+
+// ------------------------------------------------------------ host helpers
+void grid_tables(const negf_tau_grid_t* tg, std::vector<double>& w, std::vector<double>& hL,
+                 std::vector<double>& hR) {
+    const int n = tg->n_tau;
+    w.assign(n, 0.0);
+    hL.assign(n, 0.0);
+    hR.assign(n, 0.0);
+    for (int q = 0; q + 1 < n; ++q) {
+        const double h = tg->tau[q + 1] - tg->tau[q];
+        w[q] += 0.5 * h;
+        w[q + 1] += 0.5 * h;
+        hR[q] = 0.5 * h;
+        hL[q + 1] = 0.5 * h;
+    }
+}
+
+template <class T>
+int fft_tables(negf_ctx* ctx, int M, hipStream_t st, T** twist, T** tw) {
+    const std::string tag = std::string(sizeof(T) == 8 ? "fft_d_" : "fft_f_") + std::to_string(M);
+    void* p1 = nullptr;
+    void* p2 = nullptr;
+    if (!ctx->filled[tag]) {
+        std::vector<T> a(2 * M), b(M);
+        for (int q = 0; q < M; ++q) {
+            const long double th = -3.14159265358979323846264338327950288L * q / M;
+            a[2 * q] = (T)cosl(th);
+            a[2 * q + 1] = (T)sinl(th);
+        }
+        for (int k = 0; k < M / 2; ++k) {
+            const long double th = -2.0L * 3.14159265358979323846264338327950288L * k / M;
+            b[2 * k] = (T)cosl(th);
+            b[2 * k + 1] = (T)sinl(th);
+        }
+        NEGF_TRY(upload(ctx, (tag + "_twist").c_str(), a.data(), sizeof(T) * a.size(), st, &p1));
+        NEGF_TRY(upload(ctx, (tag + "_tw").c_str(), b.data(), sizeof(T) * b.size(), st, &p2));
+        ctx->filled[tag] = 1;
+    } else {
+        NEGF_TRY(scratch(ctx, (tag + "_twist").c_str(), sizeof(T) * 2 * M, &p1));
+        NEGF_TRY(scratch(ctx, (tag + "_tw").c_str(), sizeof(T) * M, &p2));
+    }
+    *twist = (T*)p1;
+    *tw = (T*)p2;
+    return NEGF_OK;
+}
+
+template <class T>
+int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0, T* out1, const T* twist,
+               const T* tw, hipStream_t st) {
+    int L = 0;
+    while ((1 << L) < M) ++L;
+    int CW = (int)(65536 / ((long)M * 2 * sizeof(T)));
+    if (CW < 1) CW = 1;
+    if (CW > 32) CW = 32;
+    const size_t smem = (size_t)CW * M * 2 * sizeof(T);
+    const long blocks = ((long)nc + 2 * CW - 1) / (2 * CW);
+    static bool attr[2][2] = {{false, false}, {false, false}};
+    const int ti = sizeof(T) == 8 ? 0 : 1;
+    if (!attr[ti][inverse]) {
+        if (inverse) HIP_TRY(hipFuncSetAttribute((const void*)k_fft_inv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        else HIP_TRY(hipFuncSetAttribute((const void*)k_fft_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr[ti][inverse] = true;
+    }
+    if (!inverse)
+        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(256), smem, st, nc, M, L, CW, in0, twist, tw,
+                           out0, out1);
+    else
+        hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(256), smem, st, nc, M, L, CW, in0, in1, twist,
+                           tw, out0);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+}  // namespace
+
+// ============================================================== Dyson step
+template <class T>
+int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const double* h, const double* V,
+              const double* eps, const double* C, double mu, const double* Sigma0, const T* G_in, const T* Sc,
+              double alpha, int symmetrize, int conv_algo, T* G_out, hipStream_t st) {
+    (void)h;
+    const int n_tau = tg->n_tau, M = n_tau - 1;
+    const long nn = (long)n * n;
+    const bool pow2 = (M & (M - 1)) == 0 && M <= 8192;
+    bool use_fft = conv_algo == NEGF_CONV_FFT ||
+                   (conv_algo == NEGF_CONV_AUTO && tg->kind == NEGF_TAU_UNIFORM && pow2);
+    const double dtau = tg->beta / M;
+
+    std::vector<double> w, hL, hR;
+    grid_tables(tg, w, hL, hR);
+    std::vector<double> tabs(4 * (size_t)n_tau);
+    for (int q = 0; q < n_tau; ++q) {
+        tabs[q] = tg->tau[q];
+        tabs[n_tau + q] = w[q];
+        tabs[2 * n_tau + q] = hL[q];
+        tabs[3 * n_tau + q] = hR[q];
+    }
+    void* dtab = nullptr;
+    NEGF_TRY(upload(ctx, "dy_grid", tabs.data(), sizeof(double) * tabs.size(), st, &dtab));
+    const double* d_tau = (const double*)dtab;
+    const double* d_w = d_tau + n_tau;
+    const double* d_hL = d_tau + 2 * n_tau;
+    const double* d_hR = d_tau + 3 * n_tau;
+
+    T *St, *I1, *It;
+    NEGF_TRY(scratch_t(ctx, "dy_St", nn, &St));
+    NEGF_TRY(scratch_t(ctx, "dy_I1", nn * n_tau, &I1));
+    NEGF_TRY(scratch_t(ctx, "dy_It", nn * n_tau, &It));
+    hipLaunchKernelGGL((k_sigma_tilde<T>), dim3(grid_for(nn)), dim3(256), 0, st, n, sigma, V,
+                       G_in + (long)M * nn, Sigma0, St);
+    LAUNCH_CHECK();
+
+    // ---------------- I1 = St G + Q[Sigma_c, G]
+    if (use_fft) {
+        const int nk = M / 2;
+        T *Are, *Aim, *Bre, *Bim, *Cre, *Cim, *twist, *tw;
+        NEGF_TRY(scratch_t(ctx, "dy_Are", nn * nk, &Are));
+        NEGF_TRY(scratch_t(ctx, "dy_Aim", nn * nk, &Aim));
+        NEGF_TRY(scratch_t(ctx, "dy_Bre", nn * nk, &Bre));
+        NEGF_TRY(scratch_t(ctx, "dy_Bim", nn * nk, &Bim));
+        NEGF_TRY(scratch_t(ctx, "dy_Cre", nn * nk, &Cre));
+        NEGF_TRY(scratch_t(ctx, "dy_Cim", nn * nk, &Cim));
+        NEGF_TRY(fft_tables<T>(ctx, M, st, &twist, &tw));
+        NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st));
+        NEGF_TRY(fft_launch<T>(false, (int)nn, M, G_in, nullptr, Bre, Bim, twist, tw, st));
+        hipLaunchKernelGGL((k_freq_prep<T>), dim3(grid_for(nn * nk)), dim3(256), 0, st, nn, nk, (T)dtau, St, Are, Aim);
+        LAUNCH_CHECK();
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Are, n, nn, Bre, n, nn, T(0), nullptr, 0, 0, Cre, n, nn, nk));
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(-1), Aim, n, nn, Bim, n, nn, T(1), Cre, n, nn, Cre, n, nn, nk));
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Are, n, nn, Bim, n, nn, T(0), nullptr, 0, 0, Cim, n, nn, nk));
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Aim, n, nn, Bre, n, nn, T(1), Cim, n, nn, Cim, n, nn, nk));
+        NEGF_TRY(fft_launch<T>(true, (int)nn, M, Cre, Cim, I1, nullptr, twist, tw, st));
+        // end points p = 0 and p = M
+        T *Lm, *Rm, *Em, *SR;
+        NEGF_TRY(scratch_t(ctx, "dy_Lm", nn, &Lm));
+        NEGF_TRY(scratch_t(ctx, "dy_Rm", nn, &Rm));
+        NEGF_TRY(scratch_t(ctx, "dy_Em", nn, &Em));
+        NEGF_TRY(scratch_t(ctx, "dy_SR", nn, &SR));
+        hipLaunchKernelGGL((k_endpoint_prep<T>), dim3(grid_for(nn)), dim3(256), 0, st, nn, (T)dtau, St, Sc,
+                           Sc + (long)M * nn, G_in, G_in + (long)M * nn, Lm, Rm);
+        LAUNCH_CHECK();
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Lm, n, 0, Rm, n, 0, T(0), nullptr, 0, 0, Em, n, 0, 1));
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), St, n, 0, Rm, n, 0, T(0), nullptr, 0, 0, SR, n, 0, 1));
+        hipLaunchKernelGGL((k_endpoint_final<T>), dim3(grid_for(nn)), dim3(256), 0, st, nn, Em, SR, I1,
+                           I1 + (long)M * nn);
+        LAUNCH_CHECK();
+    } else {
+        dim3 grid((n + 63) / 64, (n + 63) / 64, n_tau);
+        hipLaunchKernelGGL((k_conv_direct<T>), grid, dim3(256), 0, st, n, n_tau, tg->kind,
+                           tg->kind == NEGF_TAU_POWER ? tg->block : 1, d_tau, d_w, Sc, G_in, I1);
+        LAUNCH_CHECK();
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), St, n, 0, G_in, n, nn, T(1), I1, n, nn, I1, n, nn, n_tau));
+    }
+
+    // ---------------- G0 + Q[G0, I1] in the eigenbasis, rotate back, mix
+    const T* Ct = nullptr;
+    if (sizeof(T) == 8) {
+        Ct = (const T*)C;
+    } else {
+        float* Cf;
+        NEGF_TRY(scratch_t(ctx, "dy_Cf", nn, &Cf));
+        NEGF_TRY(to_f32(C, Cf, nn, st));
+        Ct = (const T*)Cf;
+    }
+    NEGF_TRY(gemm<T>(st, true, false, n, n, n, T(1), Ct, n, 0, I1, n, nn, T(0), nullptr, 0, 0, It, n, nn, n_tau));
+    double *Ea, *Eb, *dec, *cpre;
+    NEGF_TRY(scratch_t(ctx, "dy_Ea", (size_t)n * n_tau, &Ea));
+    NEGF_TRY(scratch_t(ctx, "dy_Eb", (size_t)n * n_tau, &Eb));
+    NEGF_TRY(scratch_t(ctx, "dy_dec", (size_t)n * n_tau, &dec));
+    NEGF_TRY(scratch_t(ctx, "dy_cpre", (size_t)n, &cpre));
+    hipLaunchKernelGGL(k_scan_tables, dim3(grid_for((long)n * n_tau)), dim3(256), 0, st, n, n_tau, d_tau, tg->beta,
+                       eps, mu, Ea, Eb, dec, cpre);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_eig_scan<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, n, n_tau, It, I1, d_w,
+                       d_hL, d_hR, Ea, Eb, dec, cpre, eps, mu, C);
+    LAUNCH_CHECK();
+    NEGF_TRY(gemm<T>(st, false, false, n, n, n, (T)alpha, Ct, n, 0, I1, n, nn, (T)(1.0 - alpha), G_in, n, nn, G_out,
+                     n, nn, n_tau));
+    if (symmetrize) {
+        hipLaunchKernelGGL((k_symmetrize<T>), dim3(grid_for(nn * n_tau)), dim3(256), 0, st, n, (long)n_tau, G_out);
+        LAUNCH_CHECK();
+    }
+    return NEGF_OK;
+}
+
+template <class T>
+int energy_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const double* h, const double* V,
+               const T* G, const T* Sc, double* E, double* N, hipStream_t st) {
+    const int n_tau = tg->n_tau;
+    std::vector<double> w, hL, hR;
+    grid_tables(tg, w, hL, hR);
+    void* dw = nullptr;
+    NEGF_TRY(upload(ctx, "en_w", w.data(), sizeof(double) * n_tau, st, &dw));
+    double *part, *out;
+    NEGF_TRY(scratch_t(ctx, "en_part", n_tau, &part));
+    NEGF_TRY(scratch_t(ctx, "en_out", 2, &out));
+    hipLaunchKernelGGL((k_energy_slices<T>), dim3(n_tau), dim3(256), 0, st, n, n_tau, Sc, G, part);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_energy_final<T>), dim3(1), dim3(256), 0, st, n, n_tau, sigma, h, V,
+                       G + (long)(n_tau - 1) * n * n, (const double*)dw, part, out);
+    LAUNCH_CHECK();
+    double hres[2];
+    HIP_TRY(hipMemcpyAsync(hres, out, sizeof(hres), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *E = hres[0];
+    *N = hres[1];
+    return NEGF_OK;
+}
+
+template int dyson_run<double>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
+                               const double*, const double*, double, const double*, const double*, const double*,
+                               double, int, int, double*, hipStream_t);
+template int dyson_run<float>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
+                              const double*, const double*, double, const double*, const float*, const float*,
+                              double, int, int, float*, hipStream_t);
+template int energy_run<double>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
+                                const double*, const double*, double*, double*, hipStream_t);
+template int energy_run<float>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
+                               const float*, const float*, double*, double*, hipStream_t);
+
+}  // namespace negf

@@ -1,0 +1,171 @@
+// Batched dense matrix product on the matrix cores (float64 and float32).
+//
+// C[b] = alpha * op(A[b]) diag(s[b]) op(B[b]) + beta * Cin[b]
+//
+// Workgroup tile 64 x 64, k-panel 16, four waves each owning a 32 x 32
+// quadrant (2 x 2 MFMA tiles). Panels are staged in LDS k-major so that each
+// lane's operand fetch for one MFMA is a row of 16 consecutive elements.
+#include "common.h"
+#include "mfma.h"
+
+namespace negf {
+namespace {
+
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16, GB_PAD = 2;
+
+template <class T, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, const T* __restrict__ A,
+                                              long lda, long sA, const T* __restrict__ B, long ldb,
+                                              long sB, T beta, const T* Cin, long ldci, long sCi,
+                                              T* C, long ldc, long sC, const T* __restrict__ S,
+                                              long sS) {
+    __shared__ T As[GB_K][GB_M + GB_PAD];
+    __shared__ T Bs[GB_K][GB_N + GB_PAD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const long b = blockIdx.z;
+    const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+    A += b * sA;
+    B += b * sB;
+    if (S) S += b * sS;
+    typename Mma<T>::acc_t acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mma<T>::zero();
+
+    for (int k0 = 0; k0 < K; k0 += GB_K) {
+        T ra[4], rb[4];
+        // A panel: op(A)(m, k) for m in [m0, m0+64), k in [k0, k0+16)
+        if (!TA) {
+            const int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
+            for (int e = 0; e < 4; ++e) {
+                const int k = kb + e;
+                ra[e] = (m < M && k < K) ? A[(long)m * lda + k] : T(0);
+                if (S && k < K) ra[e] *= S[k];
+            }
+        } else {
+            const int k = k0 + (tid >> 4), mb = m0 + (tid & 15) * 4;
+            for (int e = 0; e < 4; ++e) {
+                const int m = mb + e;
+                ra[e] = (m < M && k < K) ? A[(long)k * lda + m] : T(0);
+                if (S && k < K) ra[e] *= S[k];
+            }
+        }
+        if (!TB) {
+            const int k = k0 + (tid >> 4), nb = n0 + (tid & 15) * 4;
+            for (int e = 0; e < 4; ++e) {
+                const int n = nb + e;
+                rb[e] = (n < N && k < K) ? B[(long)k * ldb + n] : T(0);
+            }
+        } else {
+            const int n = n0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
+            for (int e = 0; e < 4; ++e) {
+                const int k = kb + e;
+                rb[e] = (n < N && k < K) ? B[(long)n * ldb + k] : T(0);
+            }
+        }
+        __syncthreads();
+        if (!TA) {
+            for (int e = 0; e < 4; ++e) As[(tid & 3) * 4 + e][tid >> 2] = ra[e];
+        } else {
+            for (int e = 0; e < 4; ++e) As[tid >> 4][(tid & 15) * 4 + e] = ra[e];
+        }
+        if (!TB) {
+            for (int e = 0; e < 4; ++e) Bs[tid >> 4][(tid & 15) * 4 + e] = rb[e];
+        } else {
+            for (int e = 0; e < 4; ++e) Bs[(tid & 3) * 4 + e][tid >> 2] = rb[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GB_K / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            T a0 = As[kk][wr * 32 + (lane & 15)];
+            T a1 = As[kk][wr * 32 + 16 + (lane & 15)];
+            T b0 = Bs[kk][wc * 32 + (lane & 15)];
+            T b1 = Bs[kk][wc * 32 + 16 + (lane & 15)];
+            acc[0][0] = Mma<T>::mma(a0, b0, acc[0][0]);
+            acc[0][1] = Mma<T>::mma(a0, b1, acc[0][1]);
+            acc[1][0] = Mma<T>::mma(a1, b0, acc[1][0]);
+            acc[1][1] = Mma<T>::mma(a1, b1, acc[1][1]);
+        }
+    }
+    C += b * sC;
+    if (Cin) Cin += b * sCi;
+    for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr * 32 + mi * 16 + Mma<T>::row(lane, r);
+                const int col = n0 + wc * 32 + ni * 16 + (lane & 15);
+                if (row < M && col < N) {
+                    T v = alpha * acc[mi][ni][r];
+                    if (beta != T(0)) v += beta * Cin[(long)row * ldci + col];
+                    C[(long)row * ldc + col] = v;
+                }
+            }
+}
+
+}  // namespace
+
+template <class T>
+int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha, const T* A, long lda,
+         long sA, const T* B, long ldb, long sB, T beta, const T* Cin, long ldci, long sCi, T* C,
+         long ldc, long sC, int batch, const T* S, long sS) {
+    if (M <= 0 || N <= 0 || batch <= 0) return NEGF_OK;
+    if (batch > 65535) {
+        // split very large batches over several launches
+        for (int b0 = 0; b0 < batch; b0 += 65535) {
+            int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+            NEGF_TRY(gemm<T>(st, ta, tb, M, N, K, alpha, A + (long)b0 * sA, lda, sA, B + (long)b0 * sB,
+                             ldb, sB, beta, Cin ? Cin + (long)b0 * sCi : nullptr, ldci, sCi,
+                             C + (long)b0 * sC, ldc, sC, nb, S ? S + (long)b0 * sS : nullptr, sS));
+        }
+        return NEGF_OK;
+    }
+    dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
+    if (beta != T(0) && Cin == nullptr) {
+        set_error("gemm: beta != 0 needs Cin");
+        return NEGF_EINVAL;
+    }
+#define NEGF_GEMM_LAUNCH(TA_, TB_)                                                               \
+    hipLaunchKernelGGL((k_gemm<T, TA_, TB_>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, \
+                       ldb, sB, beta, Cin, ldci, sCi, C, ldc, sC, S, sS)
+    if (!ta && !tb) NEGF_GEMM_LAUNCH(false, false);
+    else if (!ta && tb) NEGF_GEMM_LAUNCH(false, true);
+    else if (ta && !tb) NEGF_GEMM_LAUNCH(true, false);
+    else NEGF_GEMM_LAUNCH(true, true);
+#undef NEGF_GEMM_LAUNCH
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+template int gemm<double>(hipStream_t, bool, bool, int, int, int, double, const double*, long, long,
+                          const double*, long, long, double, const double*, long, long, double*,
+                          long, long, int, const double*, long);
+template int gemm<float>(hipStream_t, bool, bool, int, int, int, float, const float*, long, long,
+                         const float*, long, long, float, const float*, long, long, float*, long,
+                         long, int, const float*, long);
+
+// ---------------------------------------------------------------- conversions
+namespace {
+template <class To, class Ti>
+__global__ void k_convert(const Ti* __restrict__ in, To* __restrict__ out, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) out[i] = (To)in[i];
+}
+}  // namespace
+
+template <class Tout, class Tin>
+int convert(const Tin* in, Tout* out, size_t n, hipStream_t st) {
+    if (n == 0) return NEGF_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_convert<Tout, Tin>), dim3((unsigned)blocks), dim3(256), 0, st, in, out, n);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+template int convert<float, double>(const double*, float*, size_t, hipStream_t);
+template int convert<double, float>(const float*, double*, size_t, hipStream_t);
+
+int to_f32(const double* in, float* out, size_t n, hipStream_t st) { return convert<float, double>(in, out, n, st); }
+
+}  // namespace negf

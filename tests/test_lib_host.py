@@ -1,0 +1,101 @@
+"""Host-side checks of the C-ABI library that need no GPU: every symbol the
+header declares is exported, the host FE-DVR setup and tau grids agree with
+the oracle, and invalid arguments are rejected before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_0911_4348_amd as negf
+import workloads as W
+from oracle import fedvr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "negf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(negf.LIB_PATH):
+        from paper_0911_4348_amd import build
+        build.build()
+    return negf.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert "negf_sigma2b" in names and "fedvr_build" in names and "negf_scf" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("maker", [W.config_he, W.config_sigma_bench, W.config_h3p,
+                                   lambda: W.he_1d(bounds=W.graded_bounds(100.0, 29), n_g=7)])
+def test_fedvr_build_matches_oracle(L, maker):
+    s = maker()
+    x, Wt, T, v, V = negf.fedvr_build_system(s)
+    st = fedvr.Setup(s)
+    assert np.max(np.abs(x - st.x)) < 1e-13 * max(1, np.max(np.abs(st.x)))
+    assert np.max(np.abs(Wt - st.W)) < 1e-13
+    assert np.max(np.abs(T - st.T)) < 1e-11 * np.max(np.abs(st.T))
+    assert np.max(np.abs(v - st.v)) < 1e-13
+    assert np.max(np.abs(V - st.V)) < 1e-13
+
+
+def test_tau_grids_match_oracle(L):
+    t = negf.tau_grid("uniform", 50.0, M=1024)
+    assert np.array_equal(t, fedvr.tau_uniform(50.0, 1024))
+    t = negf.tau_grid("power", 100.0, u=64, p=16)
+    assert np.max(np.abs(t - fedvr.tau_power(100.0, 64, 16))) < 1e-14
+    assert np.all(t + t[::-1] == 100.0)
+
+
+def test_sizes_and_invalid_arguments(L):
+    assert negf.fedvr_size(40, 5) == 199
+    with pytest.raises(negf.NegfError) as e:
+        negf.fedvr_size(0, 5)
+    assert e.value.code == negf.EINVAL
+    with pytest.raises(negf.NegfError):
+        negf.tau_grid("uniform", 1.0, M=7)
+    with pytest.raises(negf.NegfError):
+        negf.fedvr_build([0.0, -1.0], 4, [0.0], [1.0])
+    # device entry points reject bad arguments before touching a device
+    rc = L.negf_sigma2b(None, 10, 5, 2, None, None, None, 0, None)
+    assert rc == negf.EINVAL
+    rc = L.negf_sigma2b(C.c_void_p(1), 0, 5, 2, C.c_void_p(8), C.c_void_p(16), C.c_void_p(24), 0, None)
+    assert rc == negf.EINVAL and b"n_b" in L.negf_last_error()
+    rc = L.negf_sigma2b(C.c_void_p(1), 10, 5, 3, C.c_void_p(8), C.c_void_p(16), C.c_void_p(24), 0, None)
+    assert rc == negf.EINVAL and b"sigma" in L.negf_last_error()
+    rc = L.negf_sigma2b(C.c_void_p(1), 10, 5, 2, C.c_void_p(8), C.c_void_p(16), C.c_void_p(16), 0, None)
+    assert rc == negf.EINVAL and b"alias" in L.negf_last_error()
+    tau = np.array([0.0, 1.0, 1.5, 3.0])
+    tg = negf.TauGrid("uniform", 3.0, tau)
+    rc = L.negf_energy(C.c_void_p(1), C.byref(tg.struct), 4, 2, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                       C.c_void_p(8), 0, None, None, None)
+    assert rc == negf.EINVAL and b"symmetric" in L.negf_last_error()
+
+
+def test_scf_rejects_bad_options(L):
+    s, keep = negf.system_struct(W.config_he())
+    o = negf.OptsT(1.5, 1e-8, 10, 0, 0, 0, 1, 0.0, 0.0, 0)
+    rc = L.negf_scf(C.c_void_p(1), C.byref(s), C.byref(o), None, None, None, None, None, None, 0, None, None, None)
+    assert rc == negf.EINVAL and b"alpha" in L.negf_last_error()
+
+
+def test_no_device_reports_enodev(L):
+    try:
+        import torch
+        has = torch.cuda.is_available()
+    except Exception:
+        has = False
+    if has:
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert L.negf_ctx_create(0, C.byref(h)) == negf.ENODEV
