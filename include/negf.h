@@ -255,6 +255,48 @@ int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* opts,
              int* iters, negf_iter_log_t* log, int log_cap, double* hf_E, double* hf_mu,
              void* stream);
 
+/* ------------------------------------------------------------------ learned initial guess */
+/* A tau-resolved float32 MLP predicts dG_ij(tau) = G(tau) - G0(tau) of the converged
+ * second-Born G from per-sample features; the guess is G_init = G0 + (dG + dG^T)/2.
+ * (Not in the paper: a production pattern around the method; the plain HF start remains
+ * the fallback.) Features of a sample (i, j, tau): x_i/10, x_j/10, v(x_i), v(x_j),
+ * Chebyshev T_0..T_15(2 tau/beta - 1), Z_1..Z_3, X_1/10..X_3/10 (nuclei zero-padded):
+ * 26 numbers. Network 26 -> 256 -> 256 -> 256 -> 1, tanh on the hidden layers;
+ * parameters are one float32 array in the order W1 (26 x 256, row-major, input-major),
+ * b1, W2 (256 x 256), b2, W3, b3, W4 (256 x 1), b4. */
+int negf_mlp_param_count(int* count);
+
+/* Feature rows F[n_samples][26] (dev, float32) for the samples (ii[s], jj[s], qq[s])
+ * (dev int32: basis indices and tau index). x, v (dev, float64, n_b), tau (dev,
+ * float64, n_tau); Xc, Zc (host, n_c <= 3). Errors: NEGF_EINVAL. */
+int negf_mlp_features(negf_ctx* ctx, int n_b, const double* x, const double* v, int n_c,
+                      const double* Xc, const double* Zc, int n_tau, const double* tau, double beta,
+                      int n_samples, const int* ii, const int* jj, const int* qq, float* F, void* stream);
+
+/* Training targets t[s] = (G[qq][ii][jj] - G0[qq][ii][jj]) / out_scale (dev). */
+int negf_mlp_targets(negf_ctx* ctx, int n_b, const double* G, const double* G0, double out_scale,
+                     int n_samples, const int* ii, const int* jj, const int* qq, float* t, void* stream);
+
+/* Network output y[s] (dev, float32) for feature rows F (dev). */
+int negf_mlp_forward(negf_ctx* ctx, const float* params, int n_samples, const float* F, float* y,
+                     void* stream);
+
+/* One training step on a mini-batch: forward, mean-squared error against target,
+ * backward, and (lr > 0) one Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrections for `step`, counted from 1) of params with moments m, v (all dev,
+ * float32, param_count entries). grad_out (dev, nullable) receives the gradient of
+ * the loss; *loss (host, nullable) the loss before the update (synchronises). */
+int negf_mlp_train_step(negf_ctx* ctx, float* params, float* m, float* v, int step, double lr,
+                        int n_samples, const float* F, const float* target, float* grad_out,
+                        double* loss, void* stream);
+
+/* Inference on the whole grid: for every q and i <= j, G_out[q][i][j] = G_out[q][j][i]
+ * = (G0[q][i][j] + G0[q][j][i])/2 + out_scale y(i, j, tau_q). x, v, tau (dev, float64);
+ * G0, G_out (dev, float64 [n_tau][n_b][n_b]; may alias). */
+int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
+                   const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,
+                   const double* tau, double beta, const double* G0, double* G_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -94,6 +94,15 @@ _SIGS = {
                               _DP, _DP, _VP]),
     "negf_scf": (C.c_int, [_VP, C.POINTER(SystemT), C.POINTER(OptsT), _VP, _VP, _DP, _DP, _IP,
                            C.POINTER(IterLogT), C.c_int, _DP, _DP, _VP]),
+    "negf_mlp_param_count": (C.c_int, [_IP]),
+    "negf_mlp_features": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP, C.c_double,
+                                    C.c_int, _VP, _VP, _VP, _VP, _VP]),
+    "negf_mlp_targets": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_int, _VP, _VP, _VP, _VP, _VP]),
+    "negf_mlp_forward": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
+    "negf_mlp_train_step": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, C.c_double, C.c_int, _VP, _VP, _VP, _DP,
+                                      _VP]),
+    "negf_mlp_guess": (C.c_int, [_VP, _VP, C.c_double, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP,
+                                 C.c_double, _VP, _VP, _VP]),
 }
 
 
@@ -362,3 +371,64 @@ def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, d
                 ms=logs[k].ms) for k in range(cap) if k == 0 or logs[k].iter != 0]
     rec = [r for r in rec if r["ms"] > 0]
     return SCFOut(G, E.value, N.value, it.value, hE.value, hmu.value, rec, rc)
+
+
+# ------------------------------------------------------------------ learned initial guess
+def mlp_param_count() -> int:
+    c = C.c_int()
+    _check(lib().negf_mlp_param_count(C.byref(c)))
+    return c.value
+
+
+def _nuclei(sysd):
+    X = np.ascontiguousarray(sysd.centres, dtype=np.float64).reshape(-1)
+    Z = np.ascontiguousarray(sysd.charges, dtype=np.float64).reshape(-1)
+    return len(X), X, Z
+
+
+def mlp_features(ctx: Context, sysd, x_d, v_d, tau_d, ii, jj, qq, stream=None):
+    """Feature rows for explicit samples; x_d, v_d, tau_d, ii, jj, qq are device tensors."""
+    torch = _torch()
+    n_c, X, Z = _nuclei(sysd)
+    S = ii.shape[0]
+    F = torch.empty((S, 26), dtype=torch.float32, device=x_d.device)
+    _check(lib().negf_mlp_features(ctx.handle, sysd.n_b, _dev_ptr(x_d), _dev_ptr(v_d), n_c, _dptr(X), _dptr(Z),
+                                   tau_d.shape[0], _dev_ptr(tau_d), float(sysd.beta), S, _dev_ptr(ii),
+                                   _dev_ptr(jj), _dev_ptr(qq), _dev_ptr(F), _stream(stream)))
+    return F
+
+
+def mlp_targets(ctx: Context, G, G0, out_scale, ii, jj, qq, stream=None):
+    torch = _torch()
+    S = ii.shape[0]
+    t = torch.empty(S, dtype=torch.float32, device=G.device)
+    _check(lib().negf_mlp_targets(ctx.handle, G.shape[1], _dev_ptr(G), _dev_ptr(G0), float(out_scale), S,
+                                  _dev_ptr(ii), _dev_ptr(jj), _dev_ptr(qq), _dev_ptr(t), _stream(stream)))
+    return t
+
+
+def mlp_forward(ctx: Context, params, F, stream=None):
+    torch = _torch()
+    y = torch.empty(F.shape[0], dtype=torch.float32, device=F.device)
+    _check(lib().negf_mlp_forward(ctx.handle, _dev_ptr(params), F.shape[0], _dev_ptr(F), _dev_ptr(y),
+                                  _stream(stream)))
+    return y
+
+
+def mlp_train_step(ctx: Context, params, m, v, step, lr, F, target, grad_out=None, want_loss=True, stream=None):
+    loss = C.c_double()
+    _check(lib().negf_mlp_train_step(ctx.handle, _dev_ptr(params), _dev_ptr(m), _dev_ptr(v), int(step), float(lr),
+                                     F.shape[0], _dev_ptr(F), _dev_ptr(target), _dev_ptr(grad_out),
+                                     C.byref(loss) if want_loss else None, _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def mlp_guess(ctx: Context, params, out_scale, sysd, x_d, v_d, tau_d, G0, G_out=None, stream=None):
+    torch = _torch()
+    n_c, X, Z = _nuclei(sysd)
+    if G_out is None:
+        G_out = torch.empty_like(G0)
+    _check(lib().negf_mlp_guess(ctx.handle, _dev_ptr(params), float(out_scale), sysd.n_b, _dev_ptr(x_d),
+                                _dev_ptr(v_d), n_c, _dptr(X), _dptr(Z), tau_d.shape[0], _dev_ptr(tau_d),
+                                float(sysd.beta), _dev_ptr(G0), _dev_ptr(G_out), _stream(stream)))
+    return G_out

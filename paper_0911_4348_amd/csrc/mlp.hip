@@ -1,0 +1,437 @@
+// Learned initial guess: a tau-resolved 4-layer MLP (float32) that predicts
+// dG_ij(tau) = G(tau) - G0(tau) from per-sample features; the guess is
+// G_init = G0 + (dG + dG^T)/2. Training and inference run in these kernels.
+//
+// Features per sample (i, j, tau): x_i/s, x_j/s, v_i, v_j, T_0..T_15(2 tau/beta - 1),
+// Z_1..Z_3, X_1/s..X_3/s (s = 10, nuclei zero-padded). Network 26 -> 256 -> 256 ->
+// 256 -> 1 with tanh hidden activations; parameters flat as W1 (26 x 256), b1,
+// W2, b2, W3, b3, W4 (256 x 1), b4. Hidden layers use the float32 matrix cores
+// with the bias and tanh fused into the product's epilogue.
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "mfma.h"
+
+namespace negf {
+namespace {
+
+constexpr int N_CHEB = 16, N_CENT = 3, D_IN = 4 + N_CHEB + 2 * N_CENT, HID = 256;
+constexpr float X_SCALE = 10.0f;
+constexpr long OFF_W1 = 0, OFF_B1 = OFF_W1 + D_IN * HID, OFF_W2 = OFF_B1 + HID, OFF_B2 = OFF_W2 + HID * HID,
+               OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + HID * HID, OFF_W4 = OFF_B3 + HID, OFF_B4 = OFF_W4 + HID,
+               N_PARAMS = OFF_B4 + 1;
+
+inline unsigned grid_for(long total) {
+    long b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+struct NucTab {
+    float Z[N_CENT];
+    float X[N_CENT];
+};
+
+__device__ __forceinline__ void feature_row(float* f, float xi, float xj, float vi, float vj, float t,
+                                            const NucTab& nt) {
+    f[0] = xi / X_SCALE;
+    f[1] = xj / X_SCALE;
+    f[2] = vi;
+    f[3] = vj;
+    float tm2 = 1.f, tm1 = t;
+    f[4] = 1.f;
+    f[5] = t;
+    for (int k = 2; k < N_CHEB; ++k) {
+        const float tk = 2.f * t * tm1 - tm2;
+        f[4 + k] = tk;
+        tm2 = tm1;
+        tm1 = tk;
+    }
+    for (int c = 0; c < N_CENT; ++c) {
+        f[4 + N_CHEB + c] = nt.Z[c];
+        f[4 + N_CHEB + N_CENT + c] = nt.X[c] / X_SCALE;
+    }
+}
+
+// Features for explicit samples (ii, jj, qq).
+__global__ void k_features(int S, const double* __restrict__ x, const double* __restrict__ v,
+                           const double* __restrict__ tau, double beta, const int* __restrict__ ii,
+                           const int* __restrict__ jj, const int* __restrict__ qq, NucTab nt, float* __restrict__ F) {
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
+        const int i = ii[s], j = jj[s], q = qq[s];
+        feature_row(F + s * D_IN, (float)x[i], (float)x[j], (float)v[i], (float)v[j],
+                    (float)(2.0 * tau[q] / beta - 1.0), nt);
+    }
+}
+
+// Features for a contiguous range of the full (q, i <= j) grid: sample s of the
+// range is global index g = g0 + s, q = g / P, pair r = g % P with (i, j) the
+// r-th upper-triangle pair in row-major order.
+__device__ __forceinline__ void pair_of(int n, long r, int* pi, int* pj) {
+    // rows i hold n - i pairs; invert the running count
+    int i = 0;
+    long base = 0;
+    // closed form start, then correct
+    double nn = n + 0.5;
+    double est = nn - sqrt(nn * nn - 2.0 * (double)r);
+    i = (int)est;
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    base = (long)i * n - (long)i * (i - 1) / 2;
+    while (i > 0 && base > r) {
+        --i;
+        base = (long)i * n - (long)i * (i - 1) / 2;
+    }
+    while (i < n - 1 && base + (n - i) <= r) {
+        base += n - i;
+        ++i;
+    }
+    *pi = i;
+    *pj = i + (int)(r - base);
+}
+
+__global__ void k_features_grid(int n, long g0, long S, const double* __restrict__ x, const double* __restrict__ v,
+                                const double* __restrict__ tau, double beta, NucTab nt, float* __restrict__ F) {
+    const long P = (long)n * (n + 1) / 2;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
+        const long g = g0 + s;
+        const int q = (int)(g / P);
+        int i, j;
+        pair_of(n, g % P, &i, &j);
+        feature_row(F + s * D_IN, (float)x[i], (float)x[j], (float)v[i], (float)v[j],
+                    (float)(2.0 * tau[q] / beta - 1.0), nt);
+    }
+}
+
+// C[S][N] = act(A[S][K] W[K][N] + b), act = tanh or identity, float32 MFMA.
+template <bool TANH>
+__global__ __launch_bounds__(256) void k_dense(int S, int K, int N, const float* __restrict__ A,
+                                               const float* __restrict__ Wt, const float* __restrict__ b,
+                                               float* __restrict__ C) {
+    __shared__ float As[16][66];
+    __shared__ float Bs[16][66];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    fv4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c) acc[a][c] = fv4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        float ra[4], rb[4];
+        {
+            const int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
+            for (int e = 0; e < 4; ++e) ra[e] = (m < S && kb + e < K) ? A[(long)m * K + kb + e] : 0.f;
+            const int k = k0 + (tid >> 4), nb = n0 + (tid & 15) * 4;
+            for (int e = 0; e < 4; ++e) rb[e] = (k < K && nb + e < N) ? Wt[(long)k * N + nb + e] : 0.f;
+        }
+        __syncthreads();
+        for (int e = 0; e < 4; ++e) As[(tid & 3) * 4 + e][tid >> 2] = ra[e];
+        for (int e = 0; e < 4; ++e) Bs[tid >> 4][(tid & 15) * 4 + e] = rb[e];
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            const float a0 = As[kk][wr * 32 + (lane & 15)], a1 = As[kk][wr * 32 + 16 + (lane & 15)];
+            const float b0 = Bs[kk][wc * 32 + (lane & 15)], b1 = Bs[kk][wc * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+    for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr * 32 + mi * 16 + Mma<float>::row(lane, r);
+                const int col = n0 + wc * 32 + ni * 16 + (lane & 15);
+                if (row < S && col < N) {
+                    float z = acc[mi][ni][r] + b[col];
+                    C[(long)row * N + col] = TANH ? tanhf(z) : z;
+                }
+            }
+}
+
+// y[s] = a3[s] . W4 + b4 (one wave per sample block)
+__global__ void k_out(int S, const float* __restrict__ a3, const float* __restrict__ W4, const float* __restrict__ b4,
+                      float* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    for (long s = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6; s < S; s += ((long)gridDim.x * blockDim.x) >> 6) {
+        float acc = 0.f;
+        for (int k = lane; k < HID; k += 64) acc += a3[s * HID + k] * W4[k];
+        acc = wave_sum(acc);
+        if (lane == 0) y[s] = acc + b4[0];
+    }
+}
+
+// dy = 2 (y - t) / S and per-block partial losses
+__global__ __launch_bounds__(256) void k_mse(int S, const float* __restrict__ y, const float* __restrict__ t,
+                                             float* __restrict__ dy, double* __restrict__ part) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
+        const float r = y[s] - t[s];
+        dy[s] = 2.f * r / (float)S;
+        acc += (double)r * r;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// d3[s][k] = dy[s] W4[k] (1 - a3^2)
+__global__ void k_back_out(int S, const float* dy, const float* W4, const float* a3, float* d3) {
+    const long tot = (long)S * HID;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const long s = e / HID;
+        const int k = (int)(e % HID);
+        const float a = a3[e];
+        d3[e] = dy[s] * W4[k] * (1.f - a * a);
+    }
+}
+
+// d *= (1 - a^2)
+__global__ void k_tanh_grad(long tot, const float* a, float* d) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const float v = a[e];
+        d[e] *= (1.f - v * v);
+    }
+}
+
+// g[c] = sum_s D[s][c] (bias gradients), one thread per column, fixed order
+__global__ void k_colsum(int S, int N, const float* D, float* g) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += D[(long)s * N + c];
+    g[c] = (float)acc;
+}
+
+// gW4[k] = sum_s a3[s][k] dy[s]
+__global__ void k_gw4(int S, const float* a3, const float* dy, float* g) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= HID) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += (double)a3[(long)s * HID + k] * dy[s];
+    g[k] = (float)acc;
+}
+
+__global__ void k_sum_dy(int S, const float* dy, float* g) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double acc = 0.0;
+        for (int s = 0; s < S; ++s) acc += dy[s];
+        g[0] = (float)acc;
+    }
+}
+
+__global__ void k_adam(long n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const float gg = g[e];
+        const float mm = b1 * m[e] + (1.f - b1) * gg;
+        const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+        m[e] = mm;
+        v[e] = vv;
+        p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    }
+}
+
+// targets t[s] = (G[q][i][j] - G0[q][i][j]) / scale
+__global__ void k_targets(int S, int n, const double* G, const double* G0, double scale, const int* ii, const int* jj,
+                          const int* qq, float* t) {
+    const long nn = (long)n * n;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
+        const long e = (long)qq[s] * nn + (long)ii[s] * n + jj[s];
+        t[s] = (float)((G[e] - G0[e]) / scale);
+    }
+}
+
+// G_out[q][i][j] = G_out[q][j][i] = G0[q][i][j] + scale y  for the range's samples
+__global__ void k_scatter_guess(int n, long g0, long S, const float* y, double scale, const double* G0, double* Gout) {
+    const long P = (long)n * (n + 1) / 2, nn = (long)n * n;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
+        const long g = g0 + s;
+        const int q = (int)(g / P);
+        int i, j;
+        pair_of(n, g % P, &i, &j);
+        const double d = scale * (double)y[s];
+        const long a = (long)q * nn + (long)i * n + j, b = (long)q * nn + (long)j * n + i;
+        // symmetric average of the two G0 entries keeps the guess exactly symmetric
+        const double base = 0.5 * (G0[a] + G0[b]);
+        Gout[a] = base + d;
+        Gout[b] = base + d;
+    }
+}
+
+NucTab make_nuc(int n_c, const double* X, const double* Z) {
+    NucTab t{};
+    for (int c = 0; c < N_CENT; ++c) {
+        t.Z[c] = c < n_c ? (float)Z[c] : 0.f;
+        t.X[c] = c < n_c ? (float)X[c] : 0.f;
+    }
+    return t;
+}
+
+int forward(negf_ctx* ctx, int S, const float* F, const float* p, float** a1, float** a2, float** a3, float* y,
+            hipStream_t st) {
+    NEGF_TRY(scratch_t(ctx, "mlp_a1", (size_t)S * HID, a1));
+    NEGF_TRY(scratch_t(ctx, "mlp_a2", (size_t)S * HID, a2));
+    NEGF_TRY(scratch_t(ctx, "mlp_a3", (size_t)S * HID, a3));
+    dim3 g(HID / 64, (S + 63) / 64);
+    hipLaunchKernelGGL((k_dense<true>), g, dim3(256), 0, st, S, D_IN, HID, F, p + OFF_W1, p + OFF_B1, *a1);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_dense<true>), g, dim3(256), 0, st, S, HID, HID, *a1, p + OFF_W2, p + OFF_B2, *a2);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_dense<true>), g, dim3(256), 0, st, S, HID, HID, *a2, p + OFF_W3, p + OFF_B3, *a3);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_out, dim3(grid_for((long)S * 64)), dim3(256), 0, st, S, *a3, p + OFF_W4, p + OFF_B4, y);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+}  // namespace
+}  // namespace negf
+
+using namespace negf;
+
+extern "C" int negf_mlp_param_count(int* count) {
+    NEGF_REQUIRE(count, "count is NULL");
+    *count = (int)N_PARAMS;
+    return NEGF_OK;
+}
+
+extern "C" int negf_mlp_features(negf_ctx* ctx, int n_b, const double* x, const double* v, int n_c,
+                                 const double* Xc, const double* Zc, int n_tau, const double* tau, double beta,
+                                 int n_samples, const int* ii, const int* jj, const int* qq, float* F, void* stream) {
+    NEGF_REQUIRE(ctx && x && v && tau && ii && jj && qq && F, "NULL argument");
+    NEGF_REQUIRE(n_b >= 1 && n_tau >= 2 && n_samples >= 1 && beta > 0, "bad sizes");
+    NEGF_REQUIRE(n_c >= 0 && n_c <= N_CENT && (n_c == 0 || (Xc && Zc)), "n_c must be 0..3");
+    NEGF_TRY(bind_device(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_features, dim3(grid_for(n_samples)), dim3(256), 0, st, n_samples, x, v, tau, beta, ii, jj, qq,
+                       make_nuc(n_c, Xc, Zc), F);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+extern "C" int negf_mlp_targets(negf_ctx* ctx, int n_b, const double* G, const double* G0, double out_scale,
+                                int n_samples, const int* ii, const int* jj, const int* qq, float* t, void* stream) {
+    NEGF_REQUIRE(ctx && G && G0 && ii && jj && qq && t, "NULL argument");
+    NEGF_REQUIRE(n_b >= 1 && n_samples >= 1 && out_scale > 0, "bad sizes");
+    NEGF_TRY(bind_device(ctx));
+    hipLaunchKernelGGL(k_targets, dim3(grid_for(n_samples)), dim3(256), 0, (hipStream_t)stream, n_samples, n_b, G, G0,
+                       out_scale, ii, jj, qq, t);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+extern "C" int negf_mlp_forward(negf_ctx* ctx, const float* params, int n_samples, const float* F, float* y,
+                                void* stream) {
+    NEGF_REQUIRE(ctx && params && F && y, "NULL argument");
+    NEGF_REQUIRE(n_samples >= 1 && n_samples <= (1 << 26), "n_samples out of range");
+    NEGF_TRY(bind_device(ctx));
+    float *a1, *a2, *a3;
+    return forward(ctx, n_samples, F, params, &a1, &a2, &a3, y, (hipStream_t)stream);
+}
+
+extern "C" int negf_mlp_train_step(negf_ctx* ctx, float* params, float* m, float* v, int step, double lr,
+                                   int n_samples, const float* F, const float* target, float* grad_out,
+                                   double* loss, void* stream) {
+    NEGF_REQUIRE(ctx && params && m && v && F && target, "NULL argument");
+    NEGF_REQUIRE(n_samples >= 1 && n_samples <= (1 << 24), "n_samples out of range");
+    NEGF_REQUIRE(step >= 1 && lr >= 0, "step must be >= 1, lr >= 0");
+    NEGF_TRY(bind_device(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    const int S = n_samples;
+    float *a1, *a2, *a3, *y, *dy, *d3, *d2, *g;
+    double* part;
+    NEGF_TRY(scratch_t(ctx, "mlp_y", S, &y));
+    NEGF_TRY(scratch_t(ctx, "mlp_dy", S, &dy));
+    NEGF_TRY(scratch_t(ctx, "mlp_d3", (size_t)S * HID, &d3));
+    NEGF_TRY(scratch_t(ctx, "mlp_d2", (size_t)S * HID, &d2));
+    NEGF_TRY(scratch_t(ctx, "mlp_g", N_PARAMS, &g));
+    const int nblk = 256;
+    NEGF_TRY(scratch_t(ctx, "mlp_part", nblk, &part));
+    NEGF_TRY(forward(ctx, S, F, params, &a1, &a2, &a3, y, st));
+    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, st, S, y, target, dy, part);
+    LAUNCH_CHECK();
+    // output layer
+    hipLaunchKernelGGL(k_gw4, dim3(1), dim3(HID), 0, st, S, a3, dy, g + OFF_W4);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_dy, dim3(1), dim3(64), 0, st, S, dy, g + OFF_B4);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_back_out, dim3(grid_for((long)S * HID)), dim3(256), 0, st, S, dy, params + OFF_W4, a3, d3);
+    LAUNCH_CHECK();
+    // layer 3: gW3 = a2^T d3, gb3 = colsum d3, d2 = (d3 W3^T) o (1 - a2^2)
+    NEGF_TRY(gemm<float>(st, true, false, HID, HID, S, 1.f, a2, HID, 0, d3, HID, 0, 0.f, nullptr, 0, 0, g + OFF_W3, HID,
+                         0, 1));
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(HID), 0, st, S, HID, d3, g + OFF_B3);
+    LAUNCH_CHECK();
+    NEGF_TRY(gemm<float>(st, false, true, S, HID, HID, 1.f, d3, HID, 0, params + OFF_W3, HID, 0, 0.f, nullptr, 0, 0, d2,
+                         HID, 0, 1));
+    hipLaunchKernelGGL(k_tanh_grad, dim3(grid_for((long)S * HID)), dim3(256), 0, st, (long)S * HID, a2, d2);
+    LAUNCH_CHECK();
+    // layer 2: gW2 = a1^T d2, gb2, d1 = (d2 W2^T) o (1 - a1^2)   (d1 reuses d3)
+    NEGF_TRY(gemm<float>(st, true, false, HID, HID, S, 1.f, a1, HID, 0, d2, HID, 0, 0.f, nullptr, 0, 0, g + OFF_W2, HID,
+                         0, 1));
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(HID), 0, st, S, HID, d2, g + OFF_B2);
+    LAUNCH_CHECK();
+    NEGF_TRY(gemm<float>(st, false, true, S, HID, HID, 1.f, d2, HID, 0, params + OFF_W2, HID, 0, 0.f, nullptr, 0, 0, d3,
+                         HID, 0, 1));
+    hipLaunchKernelGGL(k_tanh_grad, dim3(grid_for((long)S * HID)), dim3(256), 0, st, (long)S * HID, a1, d3);
+    LAUNCH_CHECK();
+    // layer 1: gW1 = F^T d1, gb1
+    NEGF_TRY(gemm<float>(st, true, false, D_IN, HID, S, 1.f, F, D_IN, 0, d3, HID, 0, 0.f, nullptr, 0, 0, g + OFF_W1, HID,
+                         0, 1));
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(HID), 0, st, S, HID, d3, g + OFF_B1);
+    LAUNCH_CHECK();
+    if (grad_out) HIP_TRY(hipMemcpyAsync(grad_out, g, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice, st));
+    if (lr > 0) {
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+        hipLaunchKernelGGL(k_adam, dim3(grid_for(N_PARAMS)), dim3(256), 0, st, N_PARAMS, params, g, m, v, (float)lr, b1,
+                           b2, 1e-8f, c1, c2);
+        LAUNCH_CHECK();
+    }
+    if (loss) {
+        std::vector<double> hp(nblk);
+        HIP_TRY(hipMemcpyAsync(hp.data(), part, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double s = 0.0;
+        for (int k = 0; k < nblk; ++k) s += hp[k];
+        *loss = s / S;
+    }
+    return NEGF_OK;
+}
+
+extern "C" int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
+                              const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,
+                              const double* tau, double beta, const double* G0, double* G_out, void* stream) {
+    NEGF_REQUIRE(ctx && params && x && v && tau && G0 && G_out, "NULL argument");
+    NEGF_REQUIRE(n_b >= 1 && n_tau >= 2 && beta > 0 && out_scale > 0, "bad sizes");
+    NEGF_REQUIRE(n_c >= 0 && n_c <= N_CENT && (n_c == 0 || (Xc && Zc)), "n_c must be 0..3");
+    NEGF_TRY(bind_device(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    const long P = (long)n_b * (n_b + 1) / 2;
+    const long total = P * n_tau;
+    const long CH = 1L << 20;
+    float *F, *y;
+    NEGF_TRY(scratch_t(ctx, "mlp_F", (size_t)CH * D_IN, &F));
+    NEGF_TRY(scratch_t(ctx, "mlp_yg", (size_t)CH, &y));
+    const NucTab nt = make_nuc(n_c, Xc, Zc);
+    for (long g0 = 0; g0 < total; g0 += CH) {
+        const long S = total - g0 < CH ? total - g0 : CH;
+        hipLaunchKernelGGL(k_features_grid, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, x, v, tau, beta, nt, F);
+        LAUNCH_CHECK();
+        float *a1, *a2, *a3;
+        NEGF_TRY(forward(ctx, (int)S, F, params, &a1, &a2, &a3, y, st));
+        hipLaunchKernelGGL(k_scatter_guess, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, y, out_scale, G0, G_out);
+        LAUNCH_CHECK();
+    }
+    return NEGF_OK;
+}

@@ -4,37 +4,75 @@
 //   Sigma_c,ij(tau) = sum_kl V_ik V_jl [sigma G_ij G_kl Gb_lk - G_il Gb_lk G_kj],
 //   Gb = G(beta - tau).
 //
-// Slices q and q' = n_tau-1-q are done together. With symmetric slices:
-//   direct  D = V (G o Gb) V          -> Sigma_c[q] += sigma G o D, Sigma_c[q'] += sigma Gb o D
-//   exchange M^(i) = Gb diag(V_i,:) G  (one n_b x n_b x n_b product per i)
-//            X_ij  = sum_l G_il  V_jl M^(i)_lj   -> Sigma_c[q]  -= X
-//            X'_il = sum_j Gb_ij V_lj M^(i)_lj   -> Sigma_c[q'] -= X'
-// The exchange products never reach memory: a workgroup owns one slice pair
-// and IB values of i (one per wave), streams l-tiles of 16 rows of M^(i)
-// through the matrix cores with the operand A[l][k] = Gb_lk V_ik formed while
-// staging, and reduces each finished tile into X and X' in registers and LDS.
+// Slices q and q' = n_tau-1-q are done together by one kernel. For each i,
+//   M^(i) = Gb diag(V_i,:) G,  i.e.  M^(i)_lj = sum_k Gb_lk V_ik G_kj.
+// With symmetric slices everything follows from M^(i):
+//   exchange   X_ij  = sum_l G_il  V_jl M^(i)_lj   (slice q)
+//              X'_il = sum_j Gb_ij V_lj M^(i)_lj   (slice q')
+//   direct     T1_il = M^(i)_ll = sum_k V_ik G_kl Gb_lk,  D_ij = sum_l T1_il V_lj
+//   Sigma_c[q]_ij = sigma G_ij D_ij - X_ij,  Sigma_c[q']_ij = sigma Gb_ij D_ij - X'_ij.
+// The M^(i) products never reach memory: a workgroup owns one slice pair and
+// IB values of i (one per wave), streams l-tiles of 16 rows of M^(i) through
+// the matrix cores with the operand A[l][k] = Gb_lk V_ik formed while staging,
+// and folds each finished tile into X, X', T1 (registers and LDS). G is read
+// and Sigma_c written once per slice pair.
+//
+// Three arithmetic modes: float64 and float32 on the 16x16x4 MFMA shapes, and
+// bf16 operands on the 16x16x32 shape with float32 accumulation. The two
+// low-precision modes first scale every slice by an exact power of two
+// (2^e_q max|G_q| in [1/2, 1)) and unscale the result, so intermediate products
+// of small slices stay in range; only the stored float32 result can underflow.
+#include <type_traits>
+
 #include "common.h"
 #include "mfma.h"
 
 namespace negf {
 namespace {
 
-constexpr int SX_BK = 16;   // k-panel
-constexpr int SX_JB = 13;   // 16-wide column blocks per chunk (208 columns)
-constexpr int SX_PAD = 1;
+enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
 
-template <class T, int IB>
-__global__ __launch_bounds__(IB * 64) void k_sigma2b_exchange(int n, int n_tau, int n_iblk,
-                                                               const T* __restrict__ V,
-                                                               const T* __restrict__ G,
-                                                               T* __restrict__ Sc) {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int SX_JB = 13;                 // 16-wide column blocks per chunk (208 columns)
+constexpr int GS_LD = SX_JB * 16 + 1;     // row stride of the [16][208] staging tiles
+constexpr int BT_LD = 32 + 8;             // row stride (bf16) of the transposed bf16 B panel
+
+template <int MODE>
+struct Cfg {
+    typedef typename std::conditional<MODE == MODE_F64, double, float>::type T;
+    static constexpr int BK = MODE == MODE_BF16 ? 32 : 16;     // k-panel
+};
+
+template <int MODE, int IB>
+constexpr size_t stage_bytes() {
+    typedef typename Cfg<MODE>::T T;
+    // B panel: [BK][GS_LD] of T (f64/f32) or [208][BT_LD] of bf16; the same bytes
+    // later hold a [16][GS_LD] tile of V in T.
+    size_t b = MODE == MODE_BF16 ? sizeof(__bf16) * 208 * BT_LD : sizeof(T) * 16 * GS_LD;
+    size_t v = sizeof(T) * 16 * GS_LD;
+    return (b > v ? b : v + 0);
+}
+
+template <int MODE, int IB>
+__global__ __launch_bounds__(IB * 64) void k_sigma2b(int n, int n_tau, int n_iblk,
+                                                     typename Cfg<MODE>::T sigma,
+                                                     const typename Cfg<MODE>::T* __restrict__ V,
+                                                     const typename Cfg<MODE>::T* __restrict__ G,
+                                                     const int* __restrict__ ex,
+                                                     typename Cfg<MODE>::T* __restrict__ Sc) {
+    typedef typename Cfg<MODE>::T T;
+    constexpr int BK = Cfg<MODE>::BK;
     extern __shared__ unsigned char smem_raw[];
-    T* Gs = reinterpret_cast<T*>(smem_raw);                       // [SX_BK][SX_JB*16 + SX_PAD]
-    constexpr int GS_LD = SX_JB * 16 + SX_PAD;
-    T* Ab = Gs + SX_BK * GS_LD;                                   // [16][SX_BK + 1]
-    T* Vk = Ab + 16 * (SX_BK + 1);                                // [IB][SX_BK]
-    T* XPs = Vk + IB * SX_BK;                                     // [IB][np]
+    constexpr size_t SB = stage_bytes<MODE, IB>();
+    T* Gs = reinterpret_cast<T*>(smem_raw);                               // staging (B panel / V tile)
+    __bf16* Bt = reinterpret_cast<__bf16*>(smem_raw);                     // bf16 B panel, transposed
+    T* Ab = reinterpret_cast<T*>(smem_raw + ((SB + 15) & ~size_t(15)));  // [16][BK + 1]
+    T* Vk = Ab + 16 * (BK + 1);                                           // [IB][BK]
     const int np = (n + 15) & ~15;
+    T* Xs = Vk + IB * BK;                                                 // [IB][np]  X   (slice q)
+    T* XPs = Xs + IB * np;                                                // [IB][np]  X'  (slice q')
+    T* T1s = XPs + IB * np;                                               // [IB][np]  diag of M^(i)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int pair = blockIdx.x / n_iblk, iblk = blockIdx.x % n_iblk;
@@ -45,54 +83,89 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b_exchange(int n, int n_tau, 
     const T* Gb = G + (long)qb * nn;
     const int i = iblk * IB + w;
     const bool iok = i < n;
-    const int lc = lane & 15;
+    const int lc = lane & 15, lg = lane >> 4;
+    T sq = T(1), sqb = T(1);
+    if constexpr (MODE != MODE_F64) {
+        sq = (T)ldexpf(1.0f, ex[q]);
+        sqb = (T)ldexpf(1.0f, ex[qb]);
+    }
 
-    for (int e = tid; e < IB * np; e += IB * 64) XPs[e] = T(0);
+    for (int e = tid; e < 3 * IB * np; e += IB * 64) Xs[e] = T(0);
 
     for (int j0 = 0; j0 < np; j0 += SX_JB * 16) {
         const int njb = min(SX_JB, (np - j0) >> 4);
+        const int jw = njb * 16;
         T gbi[SX_JB], xcol[SX_JB];
 #pragma unroll
         for (int jb = 0; jb < SX_JB; ++jb) {
             const int j = j0 + jb * 16 + lc;
-            gbi[jb] = (iok && jb < njb && j < n) ? Gb[(long)i * n + j] : T(0);
+            gbi[jb] = (iok && jb < njb && j < n) ? Gb[(long)i * n + j] * sqb : T(0);
             xcol[jb] = T(0);
         }
         for (int l0 = 0; l0 < n; l0 += 16) {
             typename Mma<T>::acc_t acc[SX_JB];
 #pragma unroll
             for (int jb = 0; jb < SX_JB; ++jb) acc[jb] = Mma<T>::zero();
-            for (int k0 = 0; k0 < n; k0 += SX_BK) {
+            for (int k0 = 0; k0 < n; k0 += BK) {
                 __syncthreads();
-                for (int e = tid; e < SX_BK * njb * 16; e += IB * 64) {
-                    const int kk = e / (njb * 16), jj = e % (njb * 16);
+                for (int e = tid; e < BK * jw; e += IB * 64) {
+                    const int kk = e / jw, jj = e - kk * jw;
                     const int k = k0 + kk, j = j0 + jj;
-                    Gs[kk * GS_LD + jj] = (k < n && j < n) ? Gq[(long)k * n + j] : T(0);
+                    const T g = (k < n && j < n) ? Gq[(long)k * n + j] * sq : T(0);
+                    if constexpr (MODE == MODE_BF16) Bt[jj * BT_LD + kk] = (__bf16)(float)g;
+                    else Gs[kk * GS_LD + jj] = g;
                 }
-                for (int e = tid; e < 16 * SX_BK; e += IB * 64) {
-                    const int ll = e / SX_BK, kk = e % SX_BK;
+                for (int e = tid; e < 16 * BK; e += IB * 64) {
+                    const int ll = e / BK, kk = e - ll * BK;
                     const int l = l0 + ll, k = k0 + kk;
-                    Ab[ll * (SX_BK + 1) + kk] = (l < n && k < n) ? Gb[(long)l * n + k] : T(0);
+                    Ab[ll * (BK + 1) + kk] = (l < n && k < n) ? Gb[(long)l * n + k] * sqb : T(0);
                 }
-                for (int e = tid; e < IB * SX_BK; e += IB * 64) {
-                    const int ww = e / SX_BK, kk = e % SX_BK;
+                for (int e = tid; e < IB * BK; e += IB * 64) {
+                    const int ww = e / BK, kk = e - ww * BK;
                     const int ii = iblk * IB + ww, k = k0 + kk;
                     Vk[e] = (ii < n && k < n) ? V[(long)ii * n + k] : T(0);
                 }
                 __syncthreads();
+                if constexpr (MODE == MODE_BF16) {
+                    bf16x8 a;
 #pragma unroll
-                for (int ks = 0; ks < SX_BK / 4; ++ks) {
-                    const int kk = ks * 4 + (lane >> 4);
-                    const T a = Ab[lc * (SX_BK + 1) + kk] * Vk[w * SX_BK + kk];
+                    for (int e = 0; e < 8; ++e) {
+                        const int kk = lg * 8 + e;
+                        a[e] = (__bf16)(float)(Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk]);
+                    }
 #pragma unroll
                     for (int jb = 0; jb < SX_JB; ++jb)
-                        if (jb < njb) acc[jb] = Mma<T>::mma(a, Gs[kk * GS_LD + jb * 16 + lc], acc[jb]);
+                        if (jb < njb) {
+                            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[(jb * 16 + lc) * BT_LD + lg * 8]);
+                            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jb], 0, 0, 0);
+                        }
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < BK / 4; ++ks) {
+                        if (k0 + ks * 4 >= n) break;
+                        const int kk = ks * 4 + lg;
+                        const T a = Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk];
+#pragma unroll
+                        for (int jb = 0; jb < SX_JB; ++jb)
+                            if (jb < njb) acc[jb] = Mma<T>::mma(a, Gs[kk * GS_LD + jb * 16 + lc], acc[jb]);
+                    }
                 }
             }
-            // epilogue of the (l-tile, column chunk): V rows l0..l0+15 into Gs
+            // diagonal of M^(i) for rows l0..l0+15 if this chunk holds those columns
+            if (l0 >= j0 && l0 < j0 + jw) {
+                const int jd = (l0 - j0) >> 4;
+#pragma unroll
+                for (int jb = 0; jb < SX_JB; ++jb)
+                    if (jb == jd) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (Mma<T>::row(lane, r) == lc) T1s[w * np + l0 + lc] = acc[jb][r];
+                    }
+            }
+            // V rows l0..l0+15 (this chunk's columns) into the staging bytes
             __syncthreads();
-            for (int e = tid; e < 16 * njb * 16; e += IB * 64) {
-                const int ll = e / (njb * 16), jj = e % (njb * 16);
+            for (int e = tid; e < 16 * jw; e += IB * 64) {
+                const int ll = e / jw, jj = e - ll * jw;
                 const int l = l0 + ll, j = j0 + jj;
                 Gs[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
             }
@@ -101,7 +174,7 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b_exchange(int n, int n_tau, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int l = l0 + Mma<T>::row(lane, r);
-                gil[r] = (iok && l < n) ? Gq[(long)i * n + l] : T(0);
+                gil[r] = (iok && l < n) ? Gq[(long)i * n + l] * sq : T(0);
                 xp[r] = T(0);
             }
 #pragma unroll
@@ -119,71 +192,96 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b_exchange(int n, int n_tau, 
             for (int r = 0; r < 4; ++r) {
                 const T s = sum16(xp[r]);
                 const int l = l0 + Mma<T>::row(lane, r);
-                if (lc == 0 && l < np) XPs[w * np + l] += s;
+                if (lc == 0) XPs[w * np + l] += s;
             }
         }
 #pragma unroll
         for (int jb = 0; jb < SX_JB; ++jb) {
             const T s = sum4x16(xcol[jb]);
-            const int j = j0 + jb * 16 + lc;
-            if (iok && jb < njb && (lane >> 4) == 0 && j < n) Sc[(long)q * nn + (long)i * n + j] = -s;
+            if (jb < njb && lg == 0) Xs[w * np + j0 + jb * 16 + lc] = s;
         }
     }
+
+    // direct term D_ij = sum_l T1_il V_lj, then the combined, unscaled stores
+    T uq = T(1), uqb = T(1);
+    if constexpr (MODE != MODE_F64) {
+        uq = (T)ldexpf(1.0f, -(2 * ex[q] + ex[qb]));
+        uqb = (T)ldexpf(1.0f, -(ex[q] + 2 * ex[qb]));
+    }
+    constexpr int DM = (SX_JB * 16 + 63) / 64;
+    for (int j0 = 0; j0 < np; j0 += SX_JB * 16) {
+        const int jw = min(SX_JB * 16, np - j0);
+        T d[DM];
+#pragma unroll
+        for (int m = 0; m < DM; ++m) d[m] = T(0);
+        for (int l0 = 0; l0 < n; l0 += 16) {
+            __syncthreads();
+            for (int e = tid; e < 16 * jw; e += IB * 64) {
+                const int ll = e / jw, jj = e - ll * jw;
+                const int l = l0 + ll, j = j0 + jj;
+                Gs[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
+            }
+            __syncthreads();
+            for (int ll = 0; ll < 16; ++ll) {
+                const T t = (l0 + ll < n) ? T1s[w * np + l0 + ll] : T(0);
+#pragma unroll
+                for (int m = 0; m < DM; ++m)
+                    if (lane + 64 * m < jw) d[m] += t * Gs[ll * GS_LD + lane + 64 * m];
+            }
+        }
+        if (iok) {
+#pragma unroll
+            for (int m = 0; m < DM; ++m) {
+                const int j = j0 + lane + 64 * m;
+                if (lane + 64 * m < jw && j < n) {
+                    const long ij = (long)i * n + j;
+                    Sc[(long)q * nn + ij] = (sigma * (Gq[ij] * sq) * d[m] - Xs[w * np + j]) * uq;
+                    if (!middle) Sc[(long)qb * nn + ij] = (sigma * (Gb[ij] * sqb) * d[m] - XPs[w * np + j]) * uqb;
+                }
+            }
+        }
+    }
+}
+
+// ex[q] = e with 2^e max|G_q| in [1/2, 1) (0 for an all-zero slice)
+__global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __restrict__ G, int* ex) {
+    __shared__ float red[256];
+    const long nn = (long)n * n;
+    const float* g = G + (long)blockIdx.x * nn;
+    float m = 0.f;
+    for (long e = threadIdx.x; e < nn; e += 256) m = fmaxf(m, fabsf(g[e]));
+    red[threadIdx.x] = m;
     __syncthreads();
-    if (!middle && iok)
-        for (int l = lane; l < n; l += 64) Sc[(long)qb * nn + (long)i * n + l] = -XPs[w * np + l];
-}
-
-// W[t] = G[t] o G[n_tau-1-t]
-template <class T>
-__global__ void k_pair_hadamard(int n, int n_tau, int n_pairs, const T* __restrict__ G, T* __restrict__ W) {
-    const long nn = (long)n * n;
-    const long total = nn * n_pairs;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-        const long t = e / nn, r = e % nn;
-        W[e] = G[t * nn + r] * G[(n_tau - 1 - t) * nn + r];
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int e2 = 0;
+        const float mx = red[0];
+        if (mx > 0.f && isfinite(mx)) {
+            frexpf(mx, &e2);          // mx = f 2^e2, f in [1/2, 1)
+            e2 = -e2;
+            if (e2 > 100) e2 = 100;
+            if (e2 < -100) e2 = -100;
+        }
+        ex[blockIdx.x] = e2;
     }
 }
 
-// Sigma_c[q] += sigma G[q] o D[t], Sigma_c[q'] += sigma G[q'] o D[t]
-template <class T>
-__global__ void k_direct_epilogue(int n, int n_tau, int n_pairs, T sigma, const T* __restrict__ G,
-                                  const T* __restrict__ D, T* __restrict__ Sc) {
-    const long nn = (long)n * n;
-    const long total = nn * n_pairs;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-        const long t = e / nn, r = e % nn;
-        const long qb = n_tau - 1 - t;
-        const T d = D[e];
-        Sc[t * nn + r] += sigma * G[t * nn + r] * d;
-        if (qb != t) Sc[qb * nn + r] += sigma * G[qb * nn + r] * d;
-    }
-}
-
-inline unsigned grid_for(long total) {
-    long b = (total + 255) / 256;
-    if (b > 65536) b = 65536;
-    if (b < 1) b = 1;
-    return (unsigned)b;
-}
-
-}  // namespace
-
-template <class T>
-int sigma2b_run(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc,
-                bool bf16, hipStream_t st) {
-    if (bf16) {
-        set_error("bf16 exchange path not available");
-        return NEGF_EINVAL;
-    }
-    const int n_pairs = (n_tau + 1) / 2;
+template <int MODE>
+int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V,
+           const typename Cfg<MODE>::T* G, typename Cfg<MODE>::T* Sc, hipStream_t st) {
+    typedef typename Cfg<MODE>::T T;
     constexpr int IB = 8;
+    const int n_pairs = (n_tau + 1) / 2;
     const int n_iblk = (n + IB - 1) / IB;
     const int np = (n + 15) & ~15;
-    const size_t smem = sizeof(T) * ((size_t)SX_BK * (SX_JB * 16 + SX_PAD) + 16 * (SX_BK + 1) +
-                                     IB * SX_BK + (size_t)IB * np);
+    constexpr int BK = Cfg<MODE>::BK;
+    const size_t smem = ((stage_bytes<MODE, IB>() + 15) & ~size_t(15)) +
+                        sizeof(T) * (16 * (BK + 1) + IB * BK + 3 * (size_t)IB * np);
     if (smem > 160 * 1024) {
-        set_error("n_b = %d too large for the exchange kernel's LDS budget", n);
+        set_error("n_b = %d too large for the Sigma-2B kernel's LDS budget", n);
         return NEGF_EINVAL;
     }
     const long blocks = (long)n_pairs * n_iblk;
@@ -191,33 +289,32 @@ int sigma2b_run(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T*
         set_error("too many workgroups");
         return NEGF_EINVAL;
     }
-    static bool attr_set[2] = {false, false};
-    const int ti = sizeof(T) == 8 ? 0 : 1;
-    if (!attr_set[ti]) {
-        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b_exchange<T, IB>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set[ti] = true;
+    int* ex = nullptr;
+    if (MODE != MODE_F64) {
+        NEGF_TRY(scratch_t(ctx, "s2b_ex", n_tau, &ex));
+        hipLaunchKernelGGL(k_slice_exponent, dim3(n_tau), dim3(256), 0, st, n, (const float*)G, ex);
+        LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL((k_sigma2b_exchange<T, IB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st,
-                       n, n_tau, n_iblk, V, G, Sc);
-    LAUNCH_CHECK();
-
-    // direct term
-    const long nn = (long)n * n;
-    T *W = nullptr, *T1 = nullptr;
-    NEGF_TRY(scratch_t(ctx, "s2b_w", (size_t)nn * n_pairs, &W));
-    NEGF_TRY(scratch_t(ctx, "s2b_t1", (size_t)nn * n_pairs, &T1));
-    hipLaunchKernelGGL((k_pair_hadamard<T>), dim3(grid_for(nn * n_pairs)), dim3(256), 0, st, n, n_tau,
-                       n_pairs, G, W);
-    LAUNCH_CHECK();
-    NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), V, n, 0, W, n, nn, T(0), nullptr, 0, 0, T1, n, nn,
-                     n_pairs));
-    NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), T1, n, nn, V, n, 0, T(0), nullptr, 0, 0, W, n, nn,
-                     n_pairs));
-    hipLaunchKernelGGL((k_direct_epilogue<T>), dim3(grid_for(nn * n_pairs)), dim3(256), 0, st, n, n_tau,
-                       n_pairs, T(sigma), G, W, Sc);
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sigma2b<MODE, IB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
+                       T(sigma), V, G, ex, Sc);
     LAUNCH_CHECK();
     return NEGF_OK;
+}
+
+}  // namespace
+
+template <class T>
+int sigma2b_run(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16,
+                hipStream_t st) {
+    if (sizeof(T) == 8) return launch<MODE_F64>(ctx, n, n_tau, sigma, (const double*)V, (const double*)G, (double*)Sc, st);
+    if (bf16) return launch<MODE_BF16>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, st);
+    return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, st);
 }
 
 template int sigma2b_run<double>(negf_ctx*, int, int, int, const double*, const double*, double*, bool, hipStream_t);

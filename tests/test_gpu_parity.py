@@ -76,8 +76,6 @@ def test_sigma2b_low_precision(ctx, torch_mod, dtype, tol):
     V = _pos_V(n, 3)
     G = W.random_symmetric_slices(n, n_tau, 4)
     ref = S.sigma2b(V, G, 2)
-    if dtype == "bf16":
-        pytest.skip("bf16 exchange path not built yet")
     out = negf.sigma2b(ctx, dev(torch_mod, V, torch_mod.float32), dev(torch_mod, G, torch_mod.float32), 2, dtype=dtype)
     err = relerr(host(out), ref)
     print(f"sigma2b {dtype} normwise error {err:.2e}")
@@ -200,9 +198,14 @@ def test_scf_fixed_iterations_direct_route(ctx):
     assert relerr(host(out.G), ref.G) < TOL64
 
 
-def test_scf_mixed_precision_energy(ctx):
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_scf_mixed_precision_energy(ctx, dtype):
+    """Low-precision loop to 1e-6 Ha, then float64 refinement: the energy error
+    against the float64 oracle is stated and must stay below 1e-6 Ha."""
     s = W.config_he()
     ref = SC.scf(s, tol=1e-10)
-    out = negf.scf(ctx, s, alpha=0.3, tol=1e-6, dtype="f32", refine_tol=1e-10)
-    print(f"mixed SCF: E={out.E:.12f} |dE|={abs(out.E - ref.E):.2e} iters={out.iters}")
+    out = negf.scf(ctx, s, alpha=0.3, tol=1e-6, dtype=dtype, refine_tol=1e-9)
+    lowp = [r for r in out.log if r["dtype"] != negf.F64]
+    print(f"mixed SCF {dtype}: E={out.E:.12f} |E-E_oracle|={abs(out.E - ref.E):.2e} Ha, "
+          f"{len(lowp)} low-precision + {out.iters - len(lowp) + 1} float64 steps")
     assert abs(out.E - ref.E) < 1e-6

@@ -197,3 +197,16 @@ def random_symmetric_slices(n_b: int, n_tau: int, seed: int, scale: float = 0.3)
 
 def random_symmetric(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     return random_symmetric_slices(n, 1, seed, scale)[0]
+
+
+def mlp_init(n_params_layers, seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters for a dense network given as [(fan_in, fan_out), ...]:
+    weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases zero, flattened layer by
+    layer (weights row-major, then biases)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for a, b in n_params_layers:
+        lim = np.sqrt(6.0 / (a + b))
+        parts.append(rng.uniform(-lim, lim, size=a * b))
+        parts.append(np.zeros(b))
+    return np.concatenate(parts)
