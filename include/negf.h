@@ -160,6 +160,19 @@ int negf_g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau, double b
 int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
                  const void* G, void* Sigma_c, int dtype, void* stream);
 
+/* Autotuner for negf_sigma2b: times each of its tile configurations (values of i
+ * per workgroup x column-chunk width) on the given input and stores the fastest
+ * for (dtype, n_b) in the context; later negf_sigma2b calls with that dtype and
+ * n_b use it. Arguments as for negf_sigma2b (Sigma_c is overwritten). *best
+ * (host, nullable) receives the chosen index, ms (host, nullable, 4 entries) the
+ * measured times (-1 for a configuration that does not fit). Synchronises. */
+int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
+                      const void* G, void* Sigma_c, int dtype, int* best, double* ms, void* stream);
+
+/* Pin the negf_sigma2b tile configuration (0..3: 8 or 4 values of i per
+ * workgroup x 208- or 112-column chunks) for (dtype, n_b) in this context. */
+int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
+
 /* ------------------------------------------------------------------ Dyson */
 typedef struct {
     int kind;                /* NEGF_TAU_UNIFORM or NEGF_TAU_POWER */

@@ -87,6 +87,8 @@ _SIGS = {
     "negf_g0_build": (C.c_int, [_VP, C.c_int, C.c_int, _DP, C.c_double, _VP, _VP, C.c_double, _VP,
                                 C.c_int, _VP]),
     "negf_sigma2b": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _VP]),
+    "negf_sigma2b_tune": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _IP, _DP, _VP]),
+    "negf_sigma2b_set_config": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int]),
     "negf_dyson_step": (C.c_int, [_VP, C.POINTER(TauGridT), C.c_int, C.c_int, _VP, _VP, _VP, _VP,
                                   C.c_double, _VP, _VP, _VP, C.c_double, C.c_int, C.c_int, C.c_int,
                                   _VP, _DP, _DP, _VP]),
@@ -300,6 +302,23 @@ def sigma2b(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=None):
     _check(lib().negf_sigma2b(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
                               _DT[dtype], _stream(stream)))
     return out
+
+
+def sigma2b_tune(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=None):
+    """negf_sigma2b_tune: returns (best config index, per-config milliseconds)."""
+    torch = _torch()
+    n_tau, n, _ = G.shape
+    if out is None:
+        out = torch.empty_like(G)
+    best = C.c_int()
+    ms = (C.c_double * 4)()
+    _check(lib().negf_sigma2b_tune(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
+                                   _DT[dtype], C.byref(best), ms, _stream(stream)))
+    return best.value, list(ms)
+
+
+def sigma2b_set_config(ctx: Context, n_b: int, dtype: str, cfg: int):
+    _check(lib().negf_sigma2b_set_config(ctx.handle, int(n_b), _DT[dtype], int(cfg)))
 
 
 def dyson_step(ctx: Context, tg: TauGrid, sigma, h, V, hfs: HFState, G_in, Sc, alpha, symmetrize=True,

@@ -362,6 +362,31 @@ extern "C" int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const 
                               (float*)Sc, dtype == NEGF_BF16, st);
 }
 
+extern "C" int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V, const void* G,
+                                 void* Sc, int dtype, int* best, double* ms, void* stream) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(n_b >= 1 && n_b <= 4096, "n_b = %d out of range [1, 4096]", n_b);
+    NEGF_REQUIRE(n_tau >= 2 && n_tau <= (1 << 20), "n_tau = %d out of range", n_tau);
+    NEGF_REQUIRE(sigma == 1 || sigma == 2, "sigma must be 1 or 2");
+    NEGF_REQUIRE(V && G && Sc, "NULL buffer");
+    NEGF_REQUIRE(G != Sc, "Sigma_c must not alias G");
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    NEGF_TRY(bind_device(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == NEGF_F64)
+        return sigma2b_tune<double>(ctx, n_b, n_tau, sigma, (const double*)V, (const double*)G, (double*)Sc, false,
+                                    best, ms, st);
+    return sigma2b_tune<float>(ctx, n_b, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc,
+                               dtype == NEGF_BF16, best, ms, st);
+}
+
+extern "C" int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(n_b >= 1 && n_b <= 4096, "n_b = %d out of range [1, 4096]", n_b);
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    return sigma2b_set_cfg(ctx, dtype, n_b, cfg);
+}
+
 // ============================================================== Dyson / energy
 namespace {
 int check_dyson_common(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, int dtype) {

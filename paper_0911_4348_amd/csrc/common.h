@@ -67,6 +67,10 @@ int g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau_host, double b
 template <class T>
 int sigma2b_run(negf_ctx* ctx, int n_b, int n_tau, int sigma, const T* V, const T* G,
                 T* Sc, bool bf16, hipStream_t st);
+int sigma2b_set_cfg(negf_ctx* ctx, int dtype, int n_b, int cfg);
+template <class T>
+int sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const T* V, const T* G, T* Sc,
+                 bool bf16, int* best, double* ms, hipStream_t st);
 
 // ---------------------------------------------------------------- Dyson
 template <class T>

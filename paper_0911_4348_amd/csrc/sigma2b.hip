@@ -22,6 +22,7 @@
 // low-precision modes first scale every slice by an exact power of two
 // (2^e_q max|G_q| in [1/2, 1)) and unscale the result, so intermediate products
 // of small slices stay in range; only the stored float32 result can underflow.
+#include <string>
 #include <type_traits>
 
 #include "common.h"
@@ -34,8 +35,6 @@ enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int SX_JB = 13;                 // 16-wide column blocks per chunk (208 columns)
-constexpr int GS_LD = SX_JB * 16 + 1;     // row stride of the [16][208] staging tiles
 constexpr int BT_LD = 32 + 8;             // row stride (bf16) of the transposed bf16 B panel
 
 template <int MODE>
@@ -44,18 +43,31 @@ struct Cfg {
     static constexpr int BK = MODE == MODE_BF16 ? 32 : 16;     // k-panel
 };
 
-template <int MODE, int IB>
+template <int MODE, int JB>
 constexpr size_t stage_bytes() {
     typedef typename Cfg<MODE>::T T;
-    // B panel: [BK][GS_LD] of T (f64/f32) or [208][BT_LD] of bf16; the same bytes
-    // later hold a [16][GS_LD] tile of V in T.
-    size_t b = MODE == MODE_BF16 ? sizeof(__bf16) * 208 * BT_LD : sizeof(T) * 16 * GS_LD;
-    size_t v = sizeof(T) * 16 * GS_LD;
+    // B panel: [BK][JB*16+1] of T (f64/f32) or [JB*16][BT_LD] of bf16; the same
+    // bytes later hold a [16][JB*16+1] tile of V in T.
+    size_t b = MODE == MODE_BF16 ? sizeof(__bf16) * JB * 16 * BT_LD : sizeof(T) * 16 * (JB * 16 + 1);
+    size_t v = sizeof(T) * 16 * (JB * 16 + 1);
     return (b > v ? b : v + 0);
 }
 
-template <int MODE, int IB>
-__global__ __launch_bounds__(IB * 64) void k_sigma2b(int n, int n_tau, int n_iblk,
+// Workgroups are handed to the 8 XCDs round-robin by block index; renumber them
+// so that each XCD receives a contiguous range of logical blocks (and with it
+// all i-blocks of the same slice pair, which then share that XCD's L2).
+__device__ __forceinline__ long xcd_remap(long b, long nb) {
+    const long x = b & 7, k = b >> 3;
+    const long base = nb >> 3, rem = nb & 7;
+    return x * base + (x < rem ? x : rem) + k;
+}
+
+// minimum waves per SIMD the register allocation must allow for a configuration
+template <int MODE, int IB, int JB>
+constexpr int waves_per_eu() { return (MODE == MODE_F64 && JB > 8) ? 2 : 4; }
+
+template <int MODE, int IB, int JB>
+__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sigma2b(int n, int n_tau, int n_iblk,
                                                      typename Cfg<MODE>::T sigma,
                                                      const typename Cfg<MODE>::T* __restrict__ V,
                                                      const typename Cfg<MODE>::T* __restrict__ G,
@@ -63,8 +75,10 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b(int n, int n_tau, int n_ibl
                                                      typename Cfg<MODE>::T* __restrict__ Sc) {
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
+    constexpr int SX_JB = JB;
+    constexpr int GS_LD = JB * 16 + 1;
     extern __shared__ unsigned char smem_raw[];
-    constexpr size_t SB = stage_bytes<MODE, IB>();
+    constexpr size_t SB = stage_bytes<MODE, JB>();
     T* Gs = reinterpret_cast<T*>(smem_raw);                               // staging (B panel / V tile)
     __bf16* Bt = reinterpret_cast<__bf16*>(smem_raw);                     // bf16 B panel, transposed
     T* Ab = reinterpret_cast<T*>(smem_raw + ((SB + 15) & ~size_t(15)));  // [16][BK + 1]
@@ -73,9 +87,11 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b(int n, int n_tau, int n_ibl
     T* Xs = Vk + IB * BK;                                                 // [IB][np]  X   (slice q)
     T* XPs = Xs + IB * np;                                                // [IB][np]  X'  (slice q')
     T* T1s = XPs + IB * np;                                               // [IB][np]  diag of M^(i)
+    T* Gbi = T1s + IB * np;                                               // [IB][np]  row i of Gb (scaled)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int pair = blockIdx.x / n_iblk, iblk = blockIdx.x % n_iblk;
+    const long lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int pair = (int)(lb / n_iblk), iblk = (int)(lb % n_iblk);
     const int q = pair, qb = n_tau - 1 - pair;
     const bool middle = (q == qb);
     const long nn = (long)n * n;
@@ -91,17 +107,18 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b(int n, int n_tau, int n_ibl
     }
 
     for (int e = tid; e < 3 * IB * np; e += IB * 64) Xs[e] = T(0);
+    for (int e = tid; e < IB * np; e += IB * 64) {
+        const int ww = e / np, j = e - ww * np;
+        const int ii = iblk * IB + ww;
+        Gbi[e] = (ii < n && j < n) ? Gb[(long)ii * n + j] * sqb : T(0);
+    }
 
     for (int j0 = 0; j0 < np; j0 += SX_JB * 16) {
         const int njb = min(SX_JB, (np - j0) >> 4);
         const int jw = njb * 16;
-        T gbi[SX_JB], xcol[SX_JB];
+        T xcol[SX_JB];
 #pragma unroll
-        for (int jb = 0; jb < SX_JB; ++jb) {
-            const int j = j0 + jb * 16 + lc;
-            gbi[jb] = (iok && jb < njb && j < n) ? Gb[(long)i * n + j] * sqb : T(0);
-            xcol[jb] = T(0);
-        }
+        for (int jb = 0; jb < SX_JB; ++jb) xcol[jb] = T(0);
         for (int l0 = 0; l0 < n; l0 += 16) {
             typename Mma<T>::acc_t acc[SX_JB];
 #pragma unroll
@@ -183,7 +200,7 @@ __global__ __launch_bounds__(IB * 64) void k_sigma2b(int n, int n_tau, int n_ibl
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const T vm = Gs[Mma<T>::row(lane, r) * GS_LD + jb * 16 + lc] * acc[jb][r];
-                        xp[r] += gbi[jb] * vm;
+                        xp[r] += Gbi[w * np + j0 + jb * 16 + lc] * vm;
                         xcol[jb] += gil[r] * vm;
                     }
                 }
@@ -269,17 +286,24 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
     }
 }
 
-template <int MODE>
-int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V,
-           const typename Cfg<MODE>::T* G, typename Cfg<MODE>::T* Sc, hipStream_t st) {
+// Tile configurations the tuner chooses from: waves (values of i) per
+// workgroup and 16-wide column blocks per chunk.
+struct TileCfg {
+    int ib, jb;
+};
+constexpr TileCfg kCfgs[] = {{8, 13}, {8, 7}, {4, 13}, {4, 7}};
+constexpr int kNumCfg = 4;
+
+template <int MODE, int IB, int JB>
+int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, const typename Cfg<MODE>::T* G,
+               const int* ex, typename Cfg<MODE>::T* Sc, hipStream_t st) {
     typedef typename Cfg<MODE>::T T;
-    constexpr int IB = 8;
     const int n_pairs = (n_tau + 1) / 2;
     const int n_iblk = (n + IB - 1) / IB;
     const int np = (n + 15) & ~15;
     constexpr int BK = Cfg<MODE>::BK;
-    const size_t smem = ((stage_bytes<MODE, IB>() + 15) & ~size_t(15)) +
-                        sizeof(T) * (16 * (BK + 1) + IB * BK + 3 * (size_t)IB * np);
+    const size_t smem = ((stage_bytes<MODE, JB>() + 15) & ~size_t(15)) +
+                        sizeof(T) * (16 * (BK + 1) + IB * BK + 4 * (size_t)IB * np);
     if (smem > 160 * 1024) {
         set_error("n_b = %d too large for the Sigma-2B kernel's LDS budget", n);
         return NEGF_EINVAL;
@@ -289,33 +313,125 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
         set_error("too many workgroups");
         return NEGF_EINVAL;
     }
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB, JB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sigma2b<MODE, IB, JB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
+                       T(sigma), V, G, ex, Sc);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+template <int MODE>
+int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V,
+           const typename Cfg<MODE>::T* G, typename Cfg<MODE>::T* Sc, int cfg, hipStream_t st) {
     int* ex = nullptr;
     if (MODE != MODE_F64) {
         NEGF_TRY(scratch_t(ctx, "s2b_ex", n_tau, &ex));
         hipLaunchKernelGGL(k_slice_exponent, dim3(n_tau), dim3(256), 0, st, n, (const float*)G, ex);
         LAUNCH_CHECK();
     }
-    static bool attr_set = false;
-    if (!attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    160 * 1024));
-        attr_set = true;
+    switch (cfg) {
+        case 0: return launch_cfg<MODE, 8, 13>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 1: return launch_cfg<MODE, 8, 7>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 2: return launch_cfg<MODE, 4, 13>(n, n_tau, sigma, V, G, ex, Sc, st);
+        default: return launch_cfg<MODE, 4, 7>(n, n_tau, sigma, V, G, ex, Sc, st);
     }
-    hipLaunchKernelGGL((k_sigma2b<MODE, IB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
-                       T(sigma), V, G, ex, Sc);
-    LAUNCH_CHECK();
+}
+
+// Default before tuning: the narrower column chunk keeps the accumulators small
+// enough for two workgroups per CU.
+int default_cfg(int mode, int n) {
+    (void)mode;
+    (void)n;
+    return 1;
+}
+
+std::string tune_key(int mode, int n) { return "s2b_cfg_" + std::to_string(mode) + "_" + std::to_string(n); }
+
+}  // namespace
+
+int sigma2b_set_cfg(negf_ctx* ctx, int dtype, int n, int cfg) {
+    if (cfg < 0 || cfg >= kNumCfg) {
+        set_error("tile configuration %d out of range [0, %d)", cfg, kNumCfg);
+        return NEGF_EINVAL;
+    }
+    const int mode = dtype == NEGF_F64 ? MODE_F64 : (dtype == NEGF_BF16 ? MODE_BF16 : MODE_F32);
+    ctx->filled[tune_key(mode, n)] = cfg;
     return NEGF_OK;
 }
+
+namespace {
 
 }  // namespace
 
 template <class T>
+int sigma2b_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16, int cfg,
+                hipStream_t st);
+
+template <class T>
 int sigma2b_run(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16,
                 hipStream_t st) {
-    if (sizeof(T) == 8) return launch<MODE_F64>(ctx, n, n_tau, sigma, (const double*)V, (const double*)G, (double*)Sc, st);
-    if (bf16) return launch<MODE_BF16>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, st);
-    return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, st);
+    const int mode = sizeof(T) == 8 ? MODE_F64 : (bf16 ? MODE_BF16 : MODE_F32);
+    auto it = ctx->filled.find(tune_key(mode, n));
+    const int cfg = it != ctx->filled.end() ? it->second : default_cfg(mode, n);
+    return sigma2b_cfg<T>(ctx, n, n_tau, sigma, V, G, Sc, bf16, cfg, st);
 }
+
+template <class T>
+int sigma2b_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16, int cfg,
+                hipStream_t st) {
+    if (sizeof(T) == 8) return launch<MODE_F64>(ctx, n, n_tau, sigma, (const double*)V, (const double*)G, (double*)Sc, cfg, st);
+    if (bf16) return launch<MODE_BF16>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st);
+    return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st);
+}
+
+// Time every tile configuration on the caller's input (after one untimed
+// launch each) and remember the fastest for (mode, n_b) in the context.
+template <class T>
+int sigma2b_tune(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16, int* best,
+                 double* ms, hipStream_t st) {
+    const int mode = sizeof(T) == 8 ? MODE_F64 : (bf16 ? MODE_BF16 : MODE_F32);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int arg = -1;
+    float tbest = 0.f;
+    for (int c = 0; c < kNumCfg; ++c) {
+        int rc = sigma2b_cfg<T>(ctx, n, n_tau, sigma, V, G, Sc, bf16, c, st);
+        if (rc == NEGF_EINVAL) {          // configuration does not fit this n_b
+            if (ms) ms[c] = -1.0;
+            continue;
+        }
+        NEGF_TRY(rc);
+        HIP_TRY(hipEventRecord(e0, st));
+        NEGF_TRY(sigma2b_cfg<T>(ctx, n, n_tau, sigma, V, G, Sc, bf16, c, st));
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (ms) ms[c] = t;
+        if (arg < 0 || t < tbest) {
+            arg = c;
+            tbest = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (arg < 0) {
+        set_error("no Sigma-2B tile configuration fits n_b = %d", n);
+        return NEGF_EINVAL;
+    }
+    ctx->filled[tune_key(mode, n)] = arg;
+    if (best) *best = arg;
+    return NEGF_OK;
+}
+
+template int sigma2b_tune<double>(negf_ctx*, int, int, int, const double*, const double*, double*, bool, int*, double*, hipStream_t);
+template int sigma2b_tune<float>(negf_ctx*, int, int, int, const float*, const float*, float*, bool, int*, double*, hipStream_t);
 
 template int sigma2b_run<double>(negf_ctx*, int, int, int, const double*, const double*, double*, bool, hipStream_t);
 template int sigma2b_run<float>(negf_ctx*, int, int, int, const float*, const float*, float*, bool, hipStream_t);

@@ -61,6 +61,36 @@ def test_sigma2b_f64(ctx, torch_mod, n, n_tau):
     assert relerr(host(out), ref) < TOL64
 
 
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_sigma2b_every_tile_config(ctx, torch_mod, cfg, dtype):
+    """Every tile configuration the tuner can pick, on a size with several column
+    chunks (n > 208) and on a ragged small size."""
+    for n, n_tau in ((221, 3), (37, 5)):
+        V = _pos_V(n, 11)
+        G = W.random_symmetric_slices(n, n_tau, 12)
+        ref = S.sigma2b(V, G, 2)
+        negf.sigma2b_set_config(ctx, n, dtype, cfg)
+        if dtype == "f64":
+            out = negf.sigma2b(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
+            tol = TOL64
+        else:
+            f32 = torch_mod.float32
+            out = negf.sigma2b(ctx, dev(torch_mod, V, f32), dev(torch_mod, G, f32), 2, dtype=dtype)
+            tol = 3e-6 if dtype == "f32" else 2e-2
+        assert relerr(host(out), ref) < tol, (n, n_tau)
+
+
+def test_sigma2b_tuner(ctx, torch_mod):
+    n, n_tau = 70, 9
+    V = _pos_V(n, 13)
+    G = W.random_symmetric_slices(n, n_tau, 14)
+    best, ms = negf.sigma2b_tune(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
+    assert 0 <= best < 4 and ms[best] > 0 and all(m > 0 for m in ms)
+    out = negf.sigma2b(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
+    assert relerr(host(out), S.sigma2b(V, G, 2)) < TOL64
+
+
 def test_sigma2b_sigma1_literal(ctx, torch_mod):
     n, n_tau = 4, 3
     V = _pos_V(n, 7)
