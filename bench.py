@@ -167,7 +167,8 @@ def main():
         "roofline": {"kernel": "k_sigma2b", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None},
         "sigma2b_ms": round(sig_avg, 3),
-        "sigma2b_tuner": {"configs": ["8i x 208col", "8i x 112col", "4i x 208col", "4i x 112col"],
+        "sigma2b_tuner": {"configs": ["8i x 208col", "8i x 112col", "4i x 208col", "4i x 112col",
+                                      "8i x 112col 2-stage", "8i x 208col 2-stage"],
                           "ms": [round(m, 3) for m in tune_ms], "chosen": best},
         "dyson_ms": round(float(np.mean(dy_ms)), 3),
         "sigma2b_hbm_GBps": round(sigma2b_bytes(n, n_tau, elem) / (sig_avg * 1e-3) / 1e9, 1),

@@ -164,13 +164,15 @@ int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
  * per workgroup x column-chunk width) on the given input and stores the fastest
  * for (dtype, n_b) in the context; later negf_sigma2b calls with that dtype and
  * n_b use it. Arguments as for negf_sigma2b (Sigma_c is overwritten). *best
- * (host, nullable) receives the chosen index, ms (host, nullable, 4 entries) the
+ * (host, nullable) receives the chosen index, ms (host, nullable, 6 entries) the
  * measured times (-1 for a configuration that does not fit). Synchronises. */
 int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
                       const void* G, void* Sigma_c, int dtype, int* best, double* ms, void* stream);
 
-/* Pin the negf_sigma2b tile configuration (0..3: 8 or 4 values of i per
- * workgroup x 208- or 112-column chunks) for (dtype, n_b) in this context. */
+/* Pin the negf_sigma2b tile configuration for (dtype, n_b) in this context:
+ * 0..3 = (8 or 4 values of i per workgroup) x (208- or 112-column chunks) with
+ * single-buffered k-panels; 4, 5 = 8 x 112 and 8 x 208 with double-buffered
+ * k-panels. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
 /* ------------------------------------------------------------------ Dyson */

@@ -311,7 +311,7 @@ def sigma2b_tune(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=N
     if out is None:
         out = torch.empty_like(G)
     best = C.c_int()
-    ms = (C.c_double * 4)()
+    ms = (C.c_double * 6)()
     _check(lib().negf_sigma2b_tune(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
                                    _DT[dtype], C.byref(best), ms, _stream(stream)))
     return best.value, list(ms)

@@ -46,11 +46,20 @@ struct Cfg {
 template <int MODE, int JB>
 constexpr size_t stage_bytes() {
     typedef typename Cfg<MODE>::T T;
-    // B panel: [BK][JB*16+1] of T (f64/f32) or [JB*16][BT_LD] of bf16; the same
-    // bytes later hold a [16][JB*16+1] tile of V in T.
-    size_t b = MODE == MODE_BF16 ? sizeof(__bf16) * JB * 16 * BT_LD : sizeof(T) * 16 * (JB * 16 + 1);
+    // One staging buffer: a B panel [BK][JB*16+1] of T (f64/f32) or [JB*16][BT_LD]
+    // of bf16; buffer 0 also holds a [16][JB*16+1] tile of V in T.
+    size_t b = MODE == MODE_BF16 ? sizeof(__bf16) * JB * 16 * BT_LD
+                                 : sizeof(T) * Cfg<MODE>::BK * (JB * 16 + 1);
     size_t v = sizeof(T) * 16 * (JB * 16 + 1);
-    return (b > v ? b : v + 0);
+    return ((b > v ? b : v) + 15) & ~size_t(15);
+}
+
+template <int MODE, int IB, int JB>
+constexpr size_t lds_bytes(int np) {
+    typedef typename Cfg<MODE>::T T;
+    constexpr int BK = Cfg<MODE>::BK;
+    const int npj = (np + JB * 16 - 1) / (JB * 16) * (JB * 16);
+    return 2 * stage_bytes<MODE, JB>() + sizeof(T) * (2 * 16 * (BK + 1) + 2 * IB * BK + (size_t)IB * (np + npj));
 }
 
 // Workgroups are handed to the 8 XCDs round-robin by block index; renumber them
@@ -63,11 +72,15 @@ __device__ __forceinline__ long xcd_remap(long b, long nb) {
 }
 
 // minimum waves per SIMD the register allocation must allow for a configuration
-template <int MODE, int IB, int JB>
-constexpr int waves_per_eu() { return (MODE == MODE_F64 && JB > 8) ? 2 : 4; }
+template <int MODE, int IB, int JB, bool DB>
+constexpr int waves_per_eu() { return (DB || (MODE == MODE_F64 && JB > 8)) ? 2 : 4; }
 
-template <int MODE, int IB, int JB>
-__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sigma2b(int n, int n_tau, int n_iblk,
+// The k-panels of G (B operand), Gb (A operand rows) and V_i (A operand scale)
+// are double-buffered: while the matrix cores work on panel p from LDS, the
+// loads of panel p+1 are in flight into registers, then written to the other
+// LDS buffer; one barrier per panel.
+template <int MODE, int IB, int JB, bool DB>
+__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k_sigma2b(int n, int n_tau, int n_iblk,
                                                      typename Cfg<MODE>::T sigma,
                                                      const typename Cfg<MODE>::T* __restrict__ V,
                                                      const typename Cfg<MODE>::T* __restrict__ G,
@@ -75,19 +88,24 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sig
                                                      typename Cfg<MODE>::T* __restrict__ Sc) {
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
-    constexpr int SX_JB = JB;
+    constexpr int NT = IB * 64;
     constexpr int GS_LD = JB * 16 + 1;
+    // B-panel staging: thread t owns column t % CW of the chunk and rows
+    // t / CW + RP r of the panel (r < NSLOT)
+    constexpr int CW = JB * 16 <= 64 ? 64 : (JB * 16 <= 128 ? 128 : 256);
+    constexpr int RP = NT / CW;
+    constexpr int NSLOT = (BK + RP - 1) / RP;
+    static_assert(NT % CW == 0, "threads must cover whole staging rows");
     extern __shared__ unsigned char smem_raw[];
     constexpr size_t SB = stage_bytes<MODE, JB>();
-    T* Gs = reinterpret_cast<T*>(smem_raw);                               // staging (B panel / V tile)
-    __bf16* Bt = reinterpret_cast<__bf16*>(smem_raw);                     // bf16 B panel, transposed
-    T* Ab = reinterpret_cast<T*>(smem_raw + ((SB + 15) & ~size_t(15)));  // [16][BK + 1]
-    T* Vk = Ab + 16 * (BK + 1);                                           // [IB][BK]
+    unsigned char* stage0 = smem_raw;
+    T* Abuf = reinterpret_cast<T*>(smem_raw + 2 * SB);                    // [2][16][BK + 1]
+    T* Vbuf = Abuf + 2 * 16 * (BK + 1);                                   // [2][IB][BK]
     const int np = (n + 15) & ~15;
-    T* Xs = Vk + IB * BK;                                                 // [IB][np]  X   (slice q)
-    T* XPs = Xs + IB * np;                                                // [IB][np]  X'  (slice q')
-    T* T1s = XPs + IB * np;                                               // [IB][np]  diag of M^(i)
-    T* Gbi = T1s + IB * np;                                               // [IB][np]  row i of Gb (scaled)
+    const int npj = (np + JB * 16 - 1) / (JB * 16) * (JB * 16);          // np padded to whole chunks
+    T* T1s = Vbuf + 2 * IB * BK;                                          // [IB][np]  diag of M^(i)
+    T* Gbi = T1s + IB * np;                                               // [IB][npj] row i of Gb (scaled)
+    T* Vt = reinterpret_cast<T*>(stage0);                                 // V tile [16][GS_LD] (buffer 0)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const long lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -97,53 +115,105 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sig
     const long nn = (long)n * n;
     const T* Gq = G + (long)q * nn;
     const T* Gb = G + (long)qb * nn;
+    T* Sq = Sc + (long)q * nn;
+    T* Sqb = Sc + (long)qb * nn;
     const int i = iblk * IB + w;
     const bool iok = i < n;
     const int lc = lane & 15, lg = lane >> 4;
-    T sq = T(1), sqb = T(1);
+    T sq = T(1), sqb = T(1), uq = T(1), uqb = T(1);
     if constexpr (MODE != MODE_F64) {
         sq = (T)ldexpf(1.0f, ex[q]);
         sqb = (T)ldexpf(1.0f, ex[qb]);
+        uq = (T)ldexpf(1.0f, -(2 * ex[q] + ex[qb]));
+        uqb = (T)ldexpf(1.0f, -(ex[q] + 2 * ex[qb]));
     }
 
-    for (int e = tid; e < 3 * IB * np; e += IB * 64) Xs[e] = T(0);
-    for (int e = tid; e < IB * np; e += IB * 64) {
-        const int ww = e / np, j = e - ww * np;
+    for (int e = tid; e < IB * np; e += NT) T1s[e] = T(0);
+    for (int e = tid; e < IB * npj; e += NT) {
+        const int ww = e / npj, j = e - ww * npj;
         const int ii = iblk * IB + ww;
         Gbi[e] = (ii < n && j < n) ? Gb[(long)ii * n + j] * sqb : T(0);
     }
+    // A-operand staging: element tid + NT r of the [16][BK] panel, r < RA
+    constexpr int RA = (16 * BK + NT - 1) / NT;
+    static_assert(IB * BK <= NT, "one V_i element per thread");
+    const int v_w = tid / BK, v_kk = tid - v_w * BK;                      // valid for tid < IB BK
+    const int v_i = iblk * IB + v_w;
 
-    for (int j0 = 0; j0 < np; j0 += SX_JB * 16) {
-        const int njb = min(SX_JB, (np - j0) >> 4);
+    for (int j0 = 0; j0 < np; j0 += JB * 16) {
+        const int njb = min(JB, (np - j0) >> 4);
         const int jw = njb * 16;
-        T xcol[SX_JB];
+        const int s_jj = tid % CW, s_kk = tid / CW;
+        const bool s_col = s_jj < jw && j0 + s_jj < n;
+        T xcol[JB];
 #pragma unroll
-        for (int jb = 0; jb < SX_JB; ++jb) xcol[jb] = T(0);
+        for (int jb = 0; jb < JB; ++jb) xcol[jb] = T(0);
+
+        constexpr int NJB = JB;   // the last chunk is padded with zero columns
+#pragma unroll 1
         for (int l0 = 0; l0 < n; l0 += 16) {
-            typename Mma<T>::acc_t acc[SX_JB];
+            typename Mma<T>::acc_t acc[NJB];
 #pragma unroll
-            for (int jb = 0; jb < SX_JB; ++jb) acc[jb] = Mma<T>::zero();
-            for (int k0 = 0; k0 < n; k0 += BK) {
-                __syncthreads();
-                for (int e = tid; e < BK * jw; e += IB * 64) {
-                    const int kk = e / jw, jj = e - kk * jw;
-                    const int k = k0 + kk, j = j0 + jj;
-                    const T g = (k < n && j < n) ? Gq[(long)k * n + j] * sq : T(0);
-                    if constexpr (MODE == MODE_BF16) Bt[jj * BT_LD + kk] = (__bf16)(float)g;
-                    else Gs[kk * GS_LD + jj] = g;
+            for (int jb = 0; jb < NJB; ++jb) acc[jb] = Mma<T>::zero();
+            T rg[NSLOT], ra[RA], rv = T(0);
+            auto load = [&](int k0) {
+#pragma unroll
+                for (int r = 0; r < NSLOT; ++r) {
+                    const int kk = s_kk + RP * r, k = k0 + kk;
+                    rg[r] = (s_col && kk < BK && k < n) ? Gq[(long)k * n + j0 + s_jj] : T(0);
                 }
-                for (int e = tid; e < 16 * BK; e += IB * 64) {
-                    const int ll = e / BK, kk = e - ll * BK;
+#pragma unroll
+                for (int r = 0; r < RA; ++r) {
+                    const int e = tid + NT * r, ll = e / BK, kk = e - ll * BK;
                     const int l = l0 + ll, k = k0 + kk;
-                    Ab[ll * (BK + 1) + kk] = (l < n && k < n) ? Gb[(long)l * n + k] * sqb : T(0);
+                    ra[r] = (e < 16 * BK && l < n && k < n) ? Gb[(long)l * n + k] : T(0);
                 }
-                for (int e = tid; e < IB * BK; e += IB * 64) {
-                    const int ww = e / BK, kk = e - ww * BK;
-                    const int ii = iblk * IB + ww, k = k0 + kk;
-                    Vk[e] = (ii < n && k < n) ? V[(long)ii * n + k] : T(0);
+                if (tid < IB * BK) {
+                    const int k = k0 + v_kk;
+                    rv = (v_i < n && k < n) ? V[(long)v_i * n + k] : T(0);
                 }
+            };
+            auto store = [&](int buf) {
+                unsigned char* sb = stage0 + buf * SB;
+#pragma unroll
+                for (int r = 0; r < NSLOT; ++r) {
+                    const int kk = s_kk + RP * r;
+                    if (s_jj < JB * 16 && kk < BK) {
+                        if constexpr (MODE == MODE_BF16)
+                            reinterpret_cast<__bf16*>(sb)[s_jj * BT_LD + kk] = (__bf16)(float)(rg[r] * sq);
+                        else
+                            reinterpret_cast<T*>(sb)[kk * GS_LD + s_jj] = rg[r] * sq;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < RA; ++r) {
+                    const int e = tid + NT * r, ll = e / BK, kk = e - ll * BK;
+                    if (e < 16 * BK) Abuf[buf * 16 * (BK + 1) + ll * (BK + 1) + kk] = ra[r] * sqb;
+                }
+                if (tid < IB * BK) Vbuf[buf * IB * BK + tid] = rv;
+            };
+            const int npan = (n + BK - 1) / BK;
+            if constexpr (DB) {
+                load(0);
+                __syncthreads();                  // previous readers of buffer 0 (V tile) are done
+                store(0);
                 __syncthreads();
+            }
+#pragma unroll 1
+            for (int p = 0; p < npan; ++p) {
+                const int buf = DB ? (p & 1) : 0;
+                const bool more = DB && p + 1 < npan;
+                if constexpr (!DB) {
+                    load(p * BK);
+                    __syncthreads();
+                    store(0);
+                    __syncthreads();
+                }
+                if (more) load((p + 1) * BK);
+                const T* Ab = Abuf + buf * 16 * (BK + 1);
+                const T* Vk = Vbuf + buf * IB * BK;
                 if constexpr (MODE == MODE_BF16) {
+                    const __bf16* Bt = reinterpret_cast<const __bf16*>(stage0 + buf * SB);
                     bf16x8 a;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
@@ -151,40 +221,42 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sig
                         a[e] = (__bf16)(float)(Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk]);
                     }
 #pragma unroll
-                    for (int jb = 0; jb < SX_JB; ++jb)
-                        if (jb < njb) {
-                            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[(jb * 16 + lc) * BT_LD + lg * 8]);
-                            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jb], 0, 0, 0);
-                        }
+                    for (int jb = 0; jb < NJB; ++jb) {
+                        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[(jb * 16 + lc) * BT_LD + lg * 8]);
+                        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jb], 0, 0, 0);
+                    }
                 } else {
+                    const T* Gs = reinterpret_cast<const T*>(stage0 + buf * SB);
 #pragma unroll
                     for (int ks = 0; ks < BK / 4; ++ks) {
-                        if (k0 + ks * 4 >= n) break;
                         const int kk = ks * 4 + lg;
                         const T a = Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk];
 #pragma unroll
-                        for (int jb = 0; jb < SX_JB; ++jb)
-                            if (jb < njb) acc[jb] = Mma<T>::mma(a, Gs[kk * GS_LD + jb * 16 + lc], acc[jb]);
+                        for (int jb = 0; jb < NJB; ++jb) acc[jb] = Mma<T>::mma(a, Gs[kk * GS_LD + jb * 16 + lc], acc[jb]);
                     }
                 }
+                if constexpr (DB) {
+                    if (more) store(buf ^ 1);
+                    __syncthreads();
+                }
             }
+            if constexpr (!DB) __syncthreads();
             // diagonal of M^(i) for rows l0..l0+15 if this chunk holds those columns
             if (l0 >= j0 && l0 < j0 + jw) {
                 const int jd = (l0 - j0) >> 4;
 #pragma unroll
-                for (int jb = 0; jb < SX_JB; ++jb)
+                for (int jb = 0; jb < NJB; ++jb)
                     if (jb == jd) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
                             if (Mma<T>::row(lane, r) == lc) T1s[w * np + l0 + lc] = acc[jb][r];
                     }
             }
-            // V rows l0..l0+15 (this chunk's columns) into the staging bytes
-            __syncthreads();
-            for (int e = tid; e < 16 * jw; e += IB * 64) {
-                const int ll = e / jw, jj = e - ll * jw;
+            // V rows l0..l0+15 (this chunk's columns, zero-padded) into buffer 0
+            for (int e = tid; e < 16 * JB * 16; e += NT) {
+                const int ll = e / (JB * 16), jj = e - ll * (JB * 16);
                 const int l = l0 + ll, j = j0 + jj;
-                Gs[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
+                Vt[ll * GS_LD + jj] = (l < n && jj < jw && j < n) ? V[(long)l * n + j] : T(0);
             }
             __syncthreads();
             T gil[4], xp[4];
@@ -195,55 +267,54 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sig
                 xp[r] = T(0);
             }
 #pragma unroll
-            for (int jb = 0; jb < SX_JB; ++jb) {
-                if (jb < njb) {
+            for (int jb = 0; jb < NJB; ++jb) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const T vm = Gs[Mma<T>::row(lane, r) * GS_LD + jb * 16 + lc] * acc[jb][r];
-                        xp[r] += Gbi[w * np + j0 + jb * 16 + lc] * vm;
-                        xcol[jb] += gil[r] * vm;
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const T vm = Vt[Mma<T>::row(lane, r) * GS_LD + jb * 16 + lc] * acc[jb][r];
+                    xp[r] += Gbi[w * npj + j0 + jb * 16 + lc] * vm;
+                    xcol[jb] += gil[r] * vm;
                 }
             }
+            // X'_il (slice q'), partial over this chunk's columns: -X' uqb, accumulated in Sigma_c
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const T s = sum16(xp[r]);
+                const T sx = sum16(xp[r]);
                 const int l = l0 + Mma<T>::row(lane, r);
-                if (lc == 0) XPs[w * np + l] += s;
+                if (lc == 0 && iok && !middle && l < n) {
+                    T* dst = &Sqb[(long)i * n + l];
+                    *dst = (j0 == 0 ? T(0) : *dst) - sx * uqb;
+                }
             }
         }
+        // X_ij (slice q) for this chunk's columns: -X uq into Sigma_c
 #pragma unroll
-        for (int jb = 0; jb < SX_JB; ++jb) {
-            const T s = sum4x16(xcol[jb]);
-            if (jb < njb && lg == 0) Xs[w * np + j0 + jb * 16 + lc] = s;
+        for (int jb = 0; jb < JB; ++jb) {
+            const T sx = sum4x16(xcol[jb]);
+            const int j = j0 + jb * 16 + lc;
+            if (jb < njb && lg == 0 && iok && j < n) Sq[(long)i * n + j] = -sx * uq;
         }
     }
 
-    // direct term D_ij = sum_l T1_il V_lj, then the combined, unscaled stores
-    T uq = T(1), uqb = T(1);
-    if constexpr (MODE != MODE_F64) {
-        uq = (T)ldexpf(1.0f, -(2 * ex[q] + ex[qb]));
-        uqb = (T)ldexpf(1.0f, -(ex[q] + 2 * ex[qb]));
-    }
-    constexpr int DM = (SX_JB * 16 + 63) / 64;
-    for (int j0 = 0; j0 < np; j0 += SX_JB * 16) {
-        const int jw = min(SX_JB * 16, np - j0);
+    // direct term D_ij = sum_l T1_il V_lj, added to the exchange parts already stored
+    constexpr int DM = (JB * 16 + 63) / 64;
+    for (int j0 = 0; j0 < np; j0 += JB * 16) {
+        const int jw = min(JB * 16, np - j0);
         T d[DM];
 #pragma unroll
         for (int m = 0; m < DM; ++m) d[m] = T(0);
         for (int l0 = 0; l0 < n; l0 += 16) {
             __syncthreads();
-            for (int e = tid; e < 16 * jw; e += IB * 64) {
+            for (int e = tid; e < 16 * jw; e += NT) {
                 const int ll = e / jw, jj = e - ll * jw;
                 const int l = l0 + ll, j = j0 + jj;
-                Gs[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
+                Vt[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
             }
             __syncthreads();
             for (int ll = 0; ll < 16; ++ll) {
                 const T t = (l0 + ll < n) ? T1s[w * np + l0 + ll] : T(0);
 #pragma unroll
                 for (int m = 0; m < DM; ++m)
-                    if (lane + 64 * m < jw) d[m] += t * Gs[ll * GS_LD + lane + 64 * m];
+                    if (lane + 64 * m < jw) d[m] += t * Vt[ll * GS_LD + lane + 64 * m];
             }
         }
         if (iok) {
@@ -252,8 +323,8 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB>())) void k_sig
                 const int j = j0 + lane + 64 * m;
                 if (lane + 64 * m < jw && j < n) {
                     const long ij = (long)i * n + j;
-                    Sc[(long)q * nn + ij] = (sigma * (Gq[ij] * sq) * d[m] - Xs[w * np + j]) * uq;
-                    if (!middle) Sc[(long)qb * nn + ij] = (sigma * (Gb[ij] * sqb) * d[m] - XPs[w * np + j]) * uqb;
+                    Sq[ij] += sigma * (Gq[ij] * sq) * d[m] * uq;
+                    if (!middle) Sqb[ij] += sigma * (Gb[ij] * sqb) * d[m] * uqb;
                 }
             }
         }
@@ -288,13 +359,11 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
 
 // Tile configurations the tuner chooses from: waves (values of i) per
 // workgroup and 16-wide column blocks per chunk.
-struct TileCfg {
-    int ib, jb;
-};
-constexpr TileCfg kCfgs[] = {{8, 13}, {8, 7}, {4, 13}, {4, 7}};
-constexpr int kNumCfg = 4;
+// 0: 8 x 208 cols, 1: 8 x 112, 2: 4 x 208, 3: 4 x 112 (single-buffered staging);
+// 4: 8 x 112, 5: 8 x 208 (double-buffered staging, one workgroup per CU).
+constexpr int kNumCfg = 6;
 
-template <int MODE, int IB, int JB>
+template <int MODE, int IB, int JB, bool DB>
 int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, const typename Cfg<MODE>::T* G,
                const int* ex, typename Cfg<MODE>::T* Sc, hipStream_t st) {
     typedef typename Cfg<MODE>::T T;
@@ -302,8 +371,8 @@ int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, cons
     const int n_iblk = (n + IB - 1) / IB;
     const int np = (n + 15) & ~15;
     constexpr int BK = Cfg<MODE>::BK;
-    const size_t smem = ((stage_bytes<MODE, JB>() + 15) & ~size_t(15)) +
-                        sizeof(T) * (16 * (BK + 1) + IB * BK + 4 * (size_t)IB * np);
+    (void)BK;
+    const size_t smem = lds_bytes<MODE, IB, JB>(np);
     if (smem > 160 * 1024) {
         set_error("n_b = %d too large for the Sigma-2B kernel's LDS budget", n);
         return NEGF_EINVAL;
@@ -315,11 +384,11 @@ int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, cons
     }
     static bool attr_set = false;
     if (!attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB, JB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB, JB, DB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     160 * 1024));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sigma2b<MODE, IB, JB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
+    hipLaunchKernelGGL((k_sigma2b<MODE, IB, JB, DB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
                        T(sigma), V, G, ex, Sc);
     LAUNCH_CHECK();
     return NEGF_OK;
@@ -335,10 +404,12 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
         LAUNCH_CHECK();
     }
     switch (cfg) {
-        case 0: return launch_cfg<MODE, 8, 13>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 1: return launch_cfg<MODE, 8, 7>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 2: return launch_cfg<MODE, 4, 13>(n, n_tau, sigma, V, G, ex, Sc, st);
-        default: return launch_cfg<MODE, 4, 7>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 0: return launch_cfg<MODE, 8, 13, false>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 1: return launch_cfg<MODE, 8, 7, false>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 2: return launch_cfg<MODE, 4, 13, false>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 3: return launch_cfg<MODE, 4, 7, false>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 4: return launch_cfg<MODE, 8, 7, true>(n, n_tau, sigma, V, G, ex, Sc, st);
+        default: return launch_cfg<MODE, 8, 13, true>(n, n_tau, sigma, V, G, ex, Sc, st);
     }
 }
 

@@ -61,7 +61,7 @@ def test_sigma2b_f64(ctx, torch_mod, n, n_tau):
     assert relerr(host(out), ref) < TOL64
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_sigma2b_every_tile_config(ctx, torch_mod, cfg, dtype):
     """Every tile configuration the tuner can pick, on a size with several column
@@ -86,7 +86,7 @@ def test_sigma2b_tuner(ctx, torch_mod):
     V = _pos_V(n, 13)
     G = W.random_symmetric_slices(n, n_tau, 14)
     best, ms = negf.sigma2b_tune(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
-    assert 0 <= best < 4 and ms[best] > 0 and all(m > 0 for m in ms)
+    assert 0 <= best < 6 and ms[best] > 0 and all(m > 0 for m in ms)
     out = negf.sigma2b(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
     assert relerr(host(out), S.sigma2b(V, G, 2)) < TOL64
 
