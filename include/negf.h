@@ -171,7 +171,7 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
 
 /* Pin the negf_sigma2b tile configuration for (dtype, n_b) in this context:
  * 0..3 = (8 or 4 values of i per workgroup) x (208- or 112-column chunks) with
- * single-buffered k-panels; 4, 5 = 8 x 112 and 8 x 208 with double-buffered
+ * single-buffered k-panels; 4, 5 = 8 x 112 and 4 x 208 with double-buffered
  * k-panels. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 

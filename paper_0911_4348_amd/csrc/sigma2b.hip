@@ -54,12 +54,13 @@ constexpr size_t stage_bytes() {
     return ((b > v ? b : v) + 15) & ~size_t(15);
 }
 
-template <int MODE, int IB, int JB>
+template <int MODE, int IB, int JB, bool DB>
 constexpr size_t lds_bytes(int np) {
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
     const int npj = (np + JB * 16 - 1) / (JB * 16) * (JB * 16);
-    return 2 * stage_bytes<MODE, JB>() + sizeof(T) * (2 * 16 * (BK + 1) + 2 * IB * BK + (size_t)IB * (np + npj));
+    return (DB ? 2 : 1) * stage_bytes<MODE, JB>() +
+           sizeof(T) * (2 * 16 * (BK + 1) + 2 * IB * BK + (size_t)IB * (3 * np + npj));
 }
 
 // Workgroups are handed to the 8 XCDs round-robin by block index; renumber them
@@ -73,7 +74,12 @@ __device__ __forceinline__ long xcd_remap(long b, long nb) {
 
 // minimum waves per SIMD the register allocation must allow for a configuration
 template <int MODE, int IB, int JB, bool DB>
-constexpr int waves_per_eu() { return (DB || (MODE == MODE_F64 && JB > 8)) ? 2 : 4; }
+constexpr int waves_per_eu() {
+    // chosen so that every configuration compiles without register spills
+    if (MODE == MODE_F64) return JB > 8 ? (IB == 4 ? 1 : 2) : 2;
+    if (MODE == MODE_BF16) return JB > 8 ? (IB == 4 ? 1 : 2) : (DB ? 2 : (IB == 4 ? 2 : 4));
+    return JB > 8 ? (IB == 4 && DB ? 1 : 2) : (DB ? 3 : 4);
+}
 
 // The k-panels of G (B operand), Gb (A operand rows) and V_i (A operand scale)
 // are double-buffered: while the matrix cores work on panel p from LDS, the
@@ -99,12 +105,14 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
     extern __shared__ unsigned char smem_raw[];
     constexpr size_t SB = stage_bytes<MODE, JB>();
     unsigned char* stage0 = smem_raw;
-    T* Abuf = reinterpret_cast<T*>(smem_raw + 2 * SB);                    // [2][16][BK + 1]
+    T* Abuf = reinterpret_cast<T*>(smem_raw + (DB ? 2 : 1) * SB);         // [2][16][BK + 1]
     T* Vbuf = Abuf + 2 * 16 * (BK + 1);                                   // [2][IB][BK]
     const int np = (n + 15) & ~15;
     const int npj = (np + JB * 16 - 1) / (JB * 16) * (JB * 16);          // np padded to whole chunks
     T* T1s = Vbuf + 2 * IB * BK;                                          // [IB][np]  diag of M^(i)
-    T* Gbi = T1s + IB * np;                                               // [IB][npj] row i of Gb (scaled)
+    T* Xs = T1s + IB * np;                                                // [IB][np]  X  (slice q)
+    T* XPs = Xs + IB * np;                                                // [IB][np]  X' (slice q')
+    T* Gbi = XPs + IB * np;                                               // [IB][npj] row i of Gb (scaled)
     T* Vt = reinterpret_cast<T*>(stage0);                                 // V tile [16][GS_LD] (buffer 0)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
         uqb = (T)ldexpf(1.0f, -(ex[q] + 2 * ex[qb]));
     }
 
-    for (int e = tid; e < IB * np; e += NT) T1s[e] = T(0);
+    for (int e = tid; e < 3 * IB * np; e += NT) T1s[e] = T(0);     // T1s, Xs, XPs
     for (int e = tid; e < IB * npj; e += NT) {
         const int ww = e / npj, j = e - ww * npj;
         const int ii = iblk * IB + ww;
@@ -227,8 +235,10 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
                     }
                 } else {
                     const T* Gs = reinterpret_cast<const T*>(stage0 + buf * SB);
-#pragma unroll
-                    for (int ks = 0; ks < BK / 4; ++ks) {
+                    // k-steps of 4 that hold real rows (uniform across the workgroup)
+                    const int nks = min(BK / 4, (n - p * BK + 3) >> 2);
+#pragma unroll 4
+                    for (int ks = 0; ks < nks; ++ks) {
                         const int kk = ks * 4 + lg;
                         const T a = Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk];
 #pragma unroll
@@ -275,27 +285,23 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
                     xcol[jb] += gil[r] * vm;
                 }
             }
-            // X'_il (slice q'), partial over this chunk's columns: -X' uqb, accumulated in Sigma_c
+            // X'_il (slice q'), partial over this chunk's columns
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const T sx = sum16(xp[r]);
                 const int l = l0 + Mma<T>::row(lane, r);
-                if (lc == 0 && iok && !middle && l < n) {
-                    T* dst = &Sqb[(long)i * n + l];
-                    *dst = (j0 == 0 ? T(0) : *dst) - sx * uqb;
-                }
+                if (lc == 0) XPs[w * np + l] += sx;
             }
         }
-        // X_ij (slice q) for this chunk's columns: -X uq into Sigma_c
+        // X_ij (slice q) for this chunk's columns
 #pragma unroll
         for (int jb = 0; jb < JB; ++jb) {
             const T sx = sum4x16(xcol[jb]);
-            const int j = j0 + jb * 16 + lc;
-            if (jb < njb && lg == 0 && iok && j < n) Sq[(long)i * n + j] = -sx * uq;
+            if (jb < njb && lg == 0) Xs[w * np + j0 + jb * 16 + lc] = sx;
         }
     }
 
-    // direct term D_ij = sum_l T1_il V_lj, added to the exchange parts already stored
+    // direct term D_ij = sum_l T1_il V_lj, then one store per output element
     constexpr int DM = (JB * 16 + 63) / 64;
     for (int j0 = 0; j0 < np; j0 += JB * 16) {
         const int jw = min(JB * 16, np - j0);
@@ -323,8 +329,8 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
                 const int j = j0 + lane + 64 * m;
                 if (lane + 64 * m < jw && j < n) {
                     const long ij = (long)i * n + j;
-                    Sq[ij] += sigma * (Gq[ij] * sq) * d[m] * uq;
-                    if (!middle) Sqb[ij] += sigma * (Gb[ij] * sqb) * d[m] * uqb;
+                    Sq[ij] = (sigma * (Gq[ij] * sq) * d[m] - Xs[w * np + j]) * uq;
+                    if (!middle) Sqb[ij] = (sigma * (Gb[ij] * sqb) * d[m] - XPs[w * np + j]) * uqb;
                 }
             }
         }
@@ -360,7 +366,7 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
 // Tile configurations the tuner chooses from: waves (values of i) per
 // workgroup and 16-wide column blocks per chunk.
 // 0: 8 x 208 cols, 1: 8 x 112, 2: 4 x 208, 3: 4 x 112 (single-buffered staging);
-// 4: 8 x 112, 5: 8 x 208 (double-buffered staging, one workgroup per CU).
+// 4: 8 x 112, 5: 4 x 208 (double-buffered staging).
 constexpr int kNumCfg = 6;
 
 template <int MODE, int IB, int JB, bool DB>
@@ -372,7 +378,7 @@ int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, cons
     const int np = (n + 15) & ~15;
     constexpr int BK = Cfg<MODE>::BK;
     (void)BK;
-    const size_t smem = lds_bytes<MODE, IB, JB>(np);
+    const size_t smem = lds_bytes<MODE, IB, JB, DB>(np);
     if (smem > 160 * 1024) {
         set_error("n_b = %d too large for the Sigma-2B kernel's LDS budget", n);
         return NEGF_EINVAL;
@@ -409,7 +415,7 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
         case 2: return launch_cfg<MODE, 4, 13, false>(n, n_tau, sigma, V, G, ex, Sc, st);
         case 3: return launch_cfg<MODE, 4, 7, false>(n, n_tau, sigma, V, G, ex, Sc, st);
         case 4: return launch_cfg<MODE, 8, 7, true>(n, n_tau, sigma, V, G, ex, Sc, st);
-        default: return launch_cfg<MODE, 8, 13, true>(n, n_tau, sigma, V, G, ex, Sc, st);
+        default: return launch_cfg<MODE, 4, 13, true>(n, n_tau, sigma, V, G, ex, Sc, st);
     }
 }
 
