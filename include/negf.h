@@ -134,6 +134,20 @@ int negf_hf(negf_ctx* ctx, int n_b, const double* T, const double* v, const doub
             double* eps, double* C, double* rho, double* Sigma0,
             double* mu, double* E_hf, int* iters, void* stream);
 
+/* The same HF iteration for `batch` systems of equal size n_b at once (one
+ * Jacobi workgroup per system), e.g. a family of potentials on one grid.
+ * Device arrays are stacked with stride n_b*n_b (matrices) or n_b (vectors):
+ * T, v, V, eps, C, rho, Sigma0. Host arrays mu[batch], E_hf[batch],
+ * iters[batch] (each may be NULL). Every system keeps iterating until its own
+ * stopping rule holds; a converged system is frozen while the others go on,
+ * so each result equals what negf_hf returns for that system alone up to
+ * rounding. Errors: as negf_hf; NEGF_ENOCONV if any system did not converge
+ * (all outputs valid). Synchronises the stream. */
+int negf_hf_batched(negf_ctx* ctx, int batch, int n_b, const double* T, const double* v,
+                    const double* V, double n_elec, int sigma, double beta, double tol,
+                    int max_iter, double* eps, double* C, double* rho, double* Sigma0,
+                    double* mu, double* E_hf, int* iters, void* stream);
+
 /* HF Green's function on the tau grid (Eq. hfgf moved to tau > 0):
  * G0(tau_q) = -C diag((1 - f_k) e^(-tau_q xi_k)) C^T, xi = eps - mu, evaluated
  * with non-positive exponents only.

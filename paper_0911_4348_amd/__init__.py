@@ -84,6 +84,8 @@ _SIGS = {
     "negf_tau_grid": (C.c_int, [C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, _DP]),
     "negf_hf": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_double, C.c_int, C.c_double, C.c_double,
                           C.c_int, _VP, _VP, _VP, _VP, _DP, _DP, _IP, _VP]),
+    "negf_hf_batched": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, C.c_double, C.c_int, C.c_double, C.c_double,
+                          C.c_int, _VP, _VP, _VP, _VP, _DP, _DP, _IP, _VP]),
     "negf_g0_build": (C.c_int, [_VP, C.c_int, C.c_int, _DP, C.c_double, _VP, _VP, C.c_double, _VP,
                                 C.c_int, _VP]),
     "negf_sigma2b": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _VP]),
@@ -281,6 +283,27 @@ def hf(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1000, str
                          float(beta), float(tol), int(max_iter), _dev_ptr(eps), _dev_ptr(Cm), _dev_ptr(rho),
                          _dev_ptr(S0), C.byref(mu), C.byref(E), C.byref(it), _stream(stream)))
     return HFState(eps, Cm, rho, S0, mu.value, E.value, it.value)
+
+
+def hf_batched(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1000, stream=None):
+    """negf_hf_batched on stacked device tensors T[B,n,n], v[B,n], V[B,n,n] (float64).
+    Returns (eps[B,n], C[B,n,n], rho[B,n,n], Sigma0[B,n,n], mu[B], E_hf[B], iters[B]); the last
+    three are numpy arrays."""
+    torch = _torch()
+    B, n = v.shape
+    dev = T.device
+    eps = torch.empty((B, n), dtype=torch.float64, device=dev)
+    Cm = torch.empty((B, n, n), dtype=torch.float64, device=dev)
+    rho = torch.empty((B, n, n), dtype=torch.float64, device=dev)
+    S0 = torch.empty((B, n, n), dtype=torch.float64, device=dev)
+    mu = np.zeros(B)
+    E = np.zeros(B)
+    it = np.zeros(B, dtype=np.int32)
+    _check(lib().negf_hf_batched(ctx.handle, B, n, _dev_ptr(T), _dev_ptr(v), _dev_ptr(V), float(n_elec),
+                                 int(sigma), float(beta), float(tol), int(max_iter), _dev_ptr(eps), _dev_ptr(Cm),
+                                 _dev_ptr(rho), _dev_ptr(S0), _dptr(mu), _dptr(E),
+                                 it.ctypes.data_as(_IP), _stream(stream)))
+    return eps, Cm, rho, S0, mu, E, it
 
 
 def g0_build(ctx: Context, hfs: HFState, tau: np.ndarray, beta, dtype="f64", stream=None):

@@ -328,6 +328,24 @@ extern "C" int negf_hf(negf_ctx* ctx, int n_b, const double* T, const double* v,
                   mu, E_hf, iters, (hipStream_t)stream);
 }
 
+extern "C" int negf_hf_batched(negf_ctx* ctx, int batch, int n_b, const double* T, const double* v,
+                               const double* V, double n_elec, int sigma, double beta, double tol, int max_iter,
+                               double* eps, double* C, double* rho, double* Sigma0, double* mu, double* E_hf,
+                               int* iters, void* stream) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(batch >= 1 && batch <= 65535, "batch = %d out of range [1, 65535]", batch);
+    NEGF_REQUIRE(n_b >= 1 && n_b <= 4096, "n_b = %d out of range [1, 4096]", n_b);
+    NEGF_REQUIRE(T && v && V && eps && C && rho && Sigma0, "NULL device buffer");
+    NEGF_REQUIRE(sigma == 1 || sigma == 2, "sigma must be 1 or 2");
+    NEGF_REQUIRE(n_elec > 0 && n_elec < (double)sigma * n_b, "n_elec must be in (0, sigma n_b)");
+    NEGF_REQUIRE(beta > 0 && std::isfinite(beta), "beta must be positive");
+    NEGF_REQUIRE(tol > 0, "tol must be positive");
+    NEGF_REQUIRE(max_iter >= 1, "max_iter must be >= 1");
+    NEGF_TRY(bind_device(ctx));
+    return hf_run_batched(ctx, batch, n_b, T, v, V, n_elec, sigma, beta, tol, max_iter, eps, C, rho, Sigma0, mu,
+                          E_hf, iters, (hipStream_t)stream);
+}
+
 extern "C" int negf_g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau, double beta,
                              const double* eps, const double* C, double mu, void* G0, int dtype,
                              void* stream) {

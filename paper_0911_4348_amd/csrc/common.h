@@ -55,6 +55,9 @@ int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha,
          int batch, const T* colscale = nullptr, long sS = 0);
 
 // ---------------------------------------------------------------- HF pieces
+int hf_run_batched(negf_ctx* ctx, int B, int n_b, const double* T, const double* v, const double* V,
+                   double n_elec, int sigma, double beta, double tol, int max_iter, double* eps, double* C,
+                   double* rho, double* Sigma0, double* mu, double* E_hf, int* iters, hipStream_t st);
 int hf_run(negf_ctx* ctx, int n_b, const double* T, const double* v, const double* V,
            double n_elec, int sigma, double beta, double tol, int max_iter,
            double* eps, double* C, double* rho, double* Sigma0, double* mu, double* E_hf,

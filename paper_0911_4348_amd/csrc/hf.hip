@@ -46,12 +46,19 @@ __device__ double block_sum(double v, double* red) {
     return red[NT / 64];
 }
 
-// Cyclic Jacobi on the symmetric n x n matrix A (overwritten; its diagonal ends
-// up holding the eigenvalues); Vv accumulates the rotations (on entry the
-// basis to rotate, e.g. the identity). Pairs of one round are disjoint, so
-// their rotations are applied together: first to rows, then to columns.
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int n, double* A, double* Vv, int max_sweeps,
-                                                        double rel_tol, int* sweeps_out) {
+// Cyclic Jacobi on a batch of symmetric n x n matrices, one workgroup per
+// matrix (blockIdx.x = system; systems with active[b] == 0 are skipped).
+// A (overwritten; its diagonal ends up holding the eigenvalues) and Vt, the
+// transpose of the accumulated rotation (on entry the transpose of the basis
+// to rotate, e.g. the identity). The n/2 pairs of one round are disjoint, so
+// A <- J^T A J touches each 2 x 2 block (pair s1, pair s2) independently: one
+// thread per block reads its four entries, applies the row and the column
+// rotation, and writes them back; Vt <- J^T Vt updates rows of Vt.
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int n, long stride, double* Ab, double* Vtb, int max_sweeps,
+                                                        double rel_tol, const int* active) {
+    if (active && !active[blockIdx.x]) return;
+    double* A = Ab + blockIdx.x * stride;
+    double* Vt = Vtb + blockIdx.x * stride;
     extern __shared__ double jsm[];
     const int nn = n + (n & 1);          // even number of players (one dummy if n is odd)
     const int npair = nn / 2;
@@ -61,22 +68,19 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int n, double* A, double
     int* Q = P + npair;                  // [npair]
     double* red = reinterpret_cast<double*>(Q + npair);   // 2 npair ints keep 8-byte alignment
     const int tid = threadIdx.x;
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
-        // convergence test: off-diagonal norm against the whole norm
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double off = 0.0, all = 0.0;
         for (long e = tid; e < (long)n * n; e += JAC_THREADS) {
             const double a = A[e];
-            const long r = e / n, c = e % n;
             all += a * a;
-            if (r != c) off += a * a;
+            if (e / n != e % n) off += a * a;
         }
         off = block_sum<JAC_THREADS>(off, red);
         all = block_sum<JAC_THREADS>(all, red);
         if (off <= rel_tol * rel_tol * all) break;
         for (int round = 0; round < nn - 1; ++round) {
-            // players: position 0 fixed, the others rotate by `round`
             for (int s = tid; s < npair; s += JAC_THREADS) {
+                // players: position 0 fixed, the others rotate by `round`
                 auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (nn - 1)) + 1; };
                 int p = player(s), q = player(nn - 1 - s);
                 if (p > q) { int t = p; p = q; q = t; }
@@ -90,56 +94,57 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int n, double* A, double
                         c = 1.0 / sqrt(t * t + 1.0);
                         sv = t * c;
                     }
-                } else {
-                    p = q = -1;
                 }
                 cs[s] = c;
                 sn[s] = sv;
                 P[s] = p;
-                Q[s] = q;
+                Q[s] = q;                 // q == n marks the dummy partner
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (long e = tid; e < (long)npair * n; e += JAC_THREADS) {
-                const int s = (int)(e / n), j = (int)(e % n);
-                const int p = P[s], q = Q[s];
-                if (p < 0 || sn[s] == 0.0) continue;
-                const double c = cs[s], sv = sn[s];
-                const double ap = A[(long)p * n + j], aq = A[(long)q * n + j];
-                A[(long)p * n + j] = c * ap - sv * aq;
-                A[(long)q * n + j] = sv * ap + c * aq;
+            for (long e = tid; e < (long)npair * npair; e += JAC_THREADS) {
+                const int s1 = (int)(e / npair), s2 = (int)(e % npair);
+                const int p1 = P[s1], q1 = Q[s1], p2 = P[s2], q2 = Q[s2];
+                const double c1 = cs[s1], t1 = sn[s1], c2 = cs[s2], t2 = sn[s2];
+                const bool r1 = q1 < n, r2 = q2 < n;
+                const double a = A[(long)p1 * n + p2];
+                const double b = r2 ? A[(long)p1 * n + q2] : 0.0;
+                const double c = r1 ? A[(long)q1 * n + p2] : 0.0;
+                const double d = (r1 && r2) ? A[(long)q1 * n + q2] : 0.0;
+                // rows: (p, q) <- (c p - s q, s p + c q)
+                const double ra = c1 * a - t1 * c, rb = c1 * b - t1 * d;
+                const double rc = t1 * a + c1 * c, rd = t1 * b + c1 * d;
+                // columns likewise
+                double na = c2 * ra - t2 * rb, nb = t2 * ra + c2 * rb;
+                double nc = c2 * rc - t2 * rd, nd = t2 * rc + c2 * rd;
+                if (s1 == s2 && t1 != 0.0) { nb = 0.0; nc = 0.0; }
+                A[(long)p1 * n + p2] = na;
+                if (r2) A[(long)p1 * n + q2] = nb;
+                if (r1) A[(long)q1 * n + p2] = nc;
+                if (r1 && r2) A[(long)q1 * n + q2] = nd;
             }
-            __syncthreads();
-            // columns: A <- A J, Vv <- Vv J
             for (long e = tid; e < (long)npair * n; e += JAC_THREADS) {
                 const int s = (int)(e / n), i = (int)(e % n);
                 const int p = P[s], q = Q[s];
-                if (p < 0 || sn[s] == 0.0) continue;
-                const double c = cs[s], sv = sn[s];
-                const double ap = A[(long)i * n + p], aq = A[(long)i * n + q];
-                A[(long)i * n + p] = c * ap - sv * aq;
-                A[(long)i * n + q] = sv * ap + c * aq;
-                const double vp = Vv[(long)i * n + p], vq = Vv[(long)i * n + q];
-                Vv[(long)i * n + p] = c * vp - sv * vq;
-                Vv[(long)i * n + q] = sv * vp + c * vq;
-            }
-            __syncthreads();
-            for (int s = tid; s < npair; s += JAC_THREADS) {
-                const int p = P[s], q = Q[s];
-                if (p >= 0 && sn[s] != 0.0) {
-                    A[(long)p * n + q] = 0.0;
-                    A[(long)q * n + p] = 0.0;
-                }
+                const double sv = sn[s];
+                if (q >= n || sv == 0.0) continue;
+                const double c = cs[s];
+                const double vp = Vt[(long)p * n + i], vq = Vt[(long)q * n + i];
+                Vt[(long)p * n + i] = c * vp - sv * vq;
+                Vt[(long)q * n + i] = sv * vp + c * vq;
             }
             __syncthreads();
         }
     }
-    if (tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
-// eps = sorted diagonal of A; C = the matching columns of Vv (ascending order,
-// ties by index).
-__global__ void k_sort_eig(int n, const double* A, const double* Vv, double* eps, double* C) {
+// eps = sorted diagonal of A; C[i][rank(k)] = Vt[k][i] (ascending order, ties by index).
+__global__ void k_sort_eig(int n, long stride, const double* Ab, const double* Vtb, double* epsb, double* Cb,
+                           const int* active) {
+    if (active && !active[blockIdx.x]) return;
+    const double* A = Ab + blockIdx.x * stride;
+    const double* Vt = Vtb + blockIdx.x * stride;
+    double* eps = epsb + (long)blockIdx.x * n;
+    double* C = Cb + blockIdx.x * stride;
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
         const double ek = A[(long)k * n + k];
         int rank = 0;
@@ -148,15 +153,18 @@ __global__ void k_sort_eig(int n, const double* A, const double* Vv, double* eps
             if (ej < ek || (ej == ek && j < k)) ++rank;
         }
         eps[rank] = ek;
-        for (int i = 0; i < n; ++i) C[(long)i * n + rank] = Vv[(long)i * n + k];
+        for (int i = 0; i < n; ++i) C[(long)i * n + rank] = Vt[(long)k * n + i];
     }
 }
 
-// Chemical potential by bisection (one workgroup). For integer N/sigma = n_occ
-// the excess is sum_{k >= n_occ} f(eps_k - mu) - sum_{k < n_occ} f(mu - eps_k),
-// each term accurate even deep in the gap. Also writes f_k.
-__global__ __launch_bounds__(256) void k_mu_bisect(int n, const double* eps, double n_spin, double beta,
-                                                   double* mu_out, double* f_out) {
+// Chemical potential by bisection (one workgroup per system). For integer
+// N/sigma = n_occ the excess is sum_{k >= n_occ} f(eps_k - mu) - sum_{k < n_occ}
+// f(mu - eps_k), each term accurate even deep in the gap. Also writes f_k.
+__global__ __launch_bounds__(256) void k_mu_bisect(int n, const double* epsb, double n_spin, double beta,
+                                                   double* mub, double* fb, const int* active) {
+    if (active && !active[blockIdx.x]) return;
+    const double* eps = epsb + (long)blockIdx.x * n;
+    double* f_out = fb + (long)blockIdx.x * n;
     __shared__ double red[256 / 64 + 1];
     const int n_occ = (int)floor(n_spin + 0.5);
     const bool integer = fabs(n_spin - n_occ) < 1e-12 && n_occ >= 0 && n_occ <= n;
@@ -175,13 +183,17 @@ __global__ __launch_bounds__(256) void k_mu_bisect(int n, const double* eps, dou
         else lo = mid;
     }
     const double mu = 0.5 * (lo + hi);
-    if (threadIdx.x == 0) *mu_out = mu;
+    if (threadIdx.x == 0) mub[blockIdx.x] = mu;
     for (int k = threadIdx.x; k < n; k += 256) f_out[k] = fermi_d(eps[k] - mu, beta);
 }
 
-// F = h + Sigma^HF[rho], h = T + diag(v)
-__global__ void k_fock(int n, const double* T, const double* v, const double* V, const double* rho,
-                       int sigma, double* F, double* Sig) {
+// F = h + Sigma^HF[rho], h = T + diag(v); grid.y = system
+__global__ void k_fock(int n, long stride, const double* Tb, const double* vb, const double* Vb, const double* rhob,
+                       int sigma, double* Fb, double* Sigb, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double *T = Tb + b * stride, *V = Vb + b * stride, *rho = rhob + b * stride, *v = vb + (long)b * n;
+    double *F = Fb + b * stride, *Sig = Sigb + b * stride;
     const long nn = (long)n * n;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
         const int i = (int)(e / n), j = (int)(e % n);
@@ -196,8 +208,11 @@ __global__ void k_fock(int n, const double* T, const double* v, const double* V,
     }
 }
 
-// h = T + diag(v)
-__global__ void k_core(int n, const double* T, const double* v, double* h) {
+// h = T + diag(v); grid.y = system
+__global__ void k_core(int n, long stride, const double* Tb, const double* vb, double* hb) {
+    const int b = blockIdx.y;
+    const double *T = Tb + b * stride, *v = vb + (long)b * n;
+    double* h = hb + b * stride;
     const long nn = (long)n * n;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
         const int i = (int)(e / n), j = (int)(e % n);
@@ -205,16 +220,21 @@ __global__ void k_core(int n, const double* T, const double* v, double* h) {
     }
 }
 
-__global__ void k_identity(int n, double* I) {
+// I (or I^T, the same) per system; grid.y = system
+__global__ void k_identity(int n, long stride, double* Ib) {
+    double* I = Ib + blockIdx.y * stride;
     const long nn = (long)n * n;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
         I[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
 
-// out[0] = sigma (Tr[h rho] + Tr[Sigma^HF[rho] rho]/2), out[1] = max |rho - rho_old|
-__global__ __launch_bounds__(256) void k_hf_energy(int n, const double* T, const double* v, const double* V,
-                                                   const double* rho, const double* rho_old, int sigma,
-                                                   double* out) {
+// out[2b] = sigma (Tr[h rho] + Tr[Sigma^HF[rho] rho]/2), out[2b+1] = max |rho - rho_old|
+__global__ __launch_bounds__(256) void k_hf_energy(int n, long stride, const double* Tb, const double* vb,
+                                                   const double* Vb, const double* rhob, const double* rho_oldb,
+                                                   int sigma, double* out) {
+    const int b = blockIdx.x;
+    const double *T = Tb + b * stride, *V = Vb + b * stride, *rho = rhob + b * stride, *v = vb + (long)b * n;
+    const double* rho_old = rho_oldb ? rho_oldb + b * stride : nullptr;
     __shared__ double red[256 / 64 + 1];
     __shared__ double mred[256];
     double e1 = 0.0, e2 = 0.0, dm = 0.0;
@@ -237,8 +257,8 @@ __global__ __launch_bounds__(256) void k_hf_energy(int n, const double* T, const
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = sigma * (e1 + 0.5 * e2);
-        out[1] = mred[0];
+        out[2 * b] = sigma * (e1 + 0.5 * e2);
+        out[2 * b + 1] = mred[0];
     }
 }
 
@@ -266,103 +286,134 @@ inline unsigned grid_for(long total) {
     return (unsigned)b;
 }
 
+// out[b] = in[b]^T for B square n x n matrices
+__global__ void k_transpose(int n, long stride, const double* in, double* out) {
+    const double* a = in + blockIdx.y * stride;
+    double* o = out + blockIdx.y * stride;
+    const long nn = (long)n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
+        o[(e % n) * n + e / n] = a[e];
+}
+
+int transpose_batched(const double* in, double* out, int n, int B, hipStream_t st) {
+    const long nn = (long)n * n;
+    const unsigned g = grid_for(nn) > 256 ? 256 : grid_for(nn);
+    hipLaunchKernelGGL(k_transpose, dim3(g, B), dim3(256), 0, st, n, nn, in, out);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
 }  // namespace
 
 // ============================================================== HF driver
-int hf_run(negf_ctx* ctx, int n, const double* T, const double* v, const double* V, double n_elec,
-           int sigma, double beta, double tol, int max_iter, double* eps, double* C, double* rho,
-           double* Sigma0, double* mu_out, double* E_out, int* iters_out, hipStream_t st) {
+// B systems of the same size n, stored with stride n*n (vectors with stride n),
+// iterated in lockstep; a system stops changing once its own test passes.
+int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v, const double* V, double n_elec,
+                   int sigma, double beta, double tol, int max_iter, double* eps, double* C, double* rho,
+                   double* Sigma0, double* mu_out, double* E_out, int* iters_out, hipStream_t st) {
     const long nn = (long)n * n;
-    double *A, *Vv, *F, *Cp, *tmp, *f, *rho_old, *dmu, *dres;
-    int* dsw;
-    NEGF_TRY(scratch_t(ctx, "hf_A", nn, &A));
-    NEGF_TRY(scratch_t(ctx, "hf_V", nn, &Vv));
-    NEGF_TRY(scratch_t(ctx, "hf_F", nn, &F));
-    NEGF_TRY(scratch_t(ctx, "hf_Cp", nn, &Cp));
-    NEGF_TRY(scratch_t(ctx, "hf_tmp", nn, &tmp));
-    NEGF_TRY(scratch_t(ctx, "hf_f", n, &f));
-    NEGF_TRY(scratch_t(ctx, "hf_rho_old", nn, &rho_old));
-    NEGF_TRY(scratch_t(ctx, "hf_small", 8, &dmu));
-    dres = dmu + 2;
-    NEGF_TRY(scratch_t(ctx, "hf_sw", 4, &dsw));
+    double *A, *Vt, *F, *Cp, *tmp, *f, *rho_old, *dmu, *dres;
+    int* dact;
+    NEGF_TRY(scratch_t(ctx, "hf_A", nn * B, &A));
+    NEGF_TRY(scratch_t(ctx, "hf_Vt", nn * B, &Vt));
+    NEGF_TRY(scratch_t(ctx, "hf_F", nn * B, &F));
+    NEGF_TRY(scratch_t(ctx, "hf_Cp", nn * B, &Cp));
+    NEGF_TRY(scratch_t(ctx, "hf_tmp", nn * B, &tmp));
+    NEGF_TRY(scratch_t(ctx, "hf_f", (size_t)n * B, &f));
+    NEGF_TRY(scratch_t(ctx, "hf_rho_old", nn * B, &rho_old));
+    NEGF_TRY(scratch_t(ctx, "hf_mu", B, &dmu));
+    NEGF_TRY(scratch_t(ctx, "hf_res", 2 * B, &dres));
+    NEGF_TRY(scratch_t(ctx, "hf_act", B, &dact));
+    std::vector<int> act(B, 1), its(B, max_iter);
+    std::vector<double> E(B, 0.0), E_old(B, INFINITY), hres(2 * B);
+    HIP_TRY(hipMemcpyAsync(dact, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
 
     const int npair = (n + 1) / 2;
-    const size_t jsm = sizeof(double) * 2 * npair + sizeof(int) * 2 * npair +
-                       sizeof(double) * (JAC_THREADS / 64 + 2);
+    const size_t jsm = sizeof(double) * 2 * npair + sizeof(int) * 2 * npair + sizeof(double) * (JAC_THREADS / 64 + 2);
     const double n_spin = n_elec / sigma;
+    const dim3 g2(grid_for(nn) > 256 ? 256 : grid_for(nn), B);
 
-    // eigen-decomposition of a symmetric matrix M into (eps, C); warm start from Cprev if given
+    // eigen-decomposition of the symmetric Mx (per system) into (eps, C); warm start from Cprev
     auto eig = [&](const double* Mx, const double* Cprev) -> int {
         if (Cprev) {
-            // A = Cprev^T M Cprev, Vv = Cprev
-            NEGF_TRY(gemm<double>(st, true, false, n, n, n, 1.0, Cprev, n, 0, Mx, n, 0, 0.0, nullptr, 0, 0,
-                                  tmp, n, 0, 1));
-            NEGF_TRY(gemm<double>(st, false, false, n, n, n, 1.0, tmp, n, 0, Cprev, n, 0, 0.0, nullptr, 0, 0,
-                                  A, n, 0, 1));
-            HIP_TRY(hipMemcpyAsync(Vv, Cprev, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+            // A = Cprev^T M Cprev, Vt = Cprev^T
+            NEGF_TRY(gemm<double>(st, true, false, n, n, n, 1.0, Cprev, n, nn, Mx, n, nn, 0.0, nullptr, 0, 0, tmp, n,
+                                  nn, B));
+            NEGF_TRY(gemm<double>(st, false, false, n, n, n, 1.0, tmp, n, nn, Cprev, n, nn, 0.0, nullptr, 0, 0, A, n,
+                                  nn, B));
+            NEGF_TRY(transpose_batched(Cprev, Vt, n, B, st));
         } else {
-            HIP_TRY(hipMemcpyAsync(A, Mx, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
-            hipLaunchKernelGGL(k_identity, dim3(grid_for(nn)), dim3(256), 0, st, n, Vv);
+            HIP_TRY(hipMemcpyAsync(A, Mx, sizeof(double) * nn * B, hipMemcpyDeviceToDevice, st));
+            hipLaunchKernelGGL(k_identity, g2, dim3(256), 0, st, n, nn, Vt);
             LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), jsm, st, n, A, Vv, 60, 1e-15, dsw);
+        hipLaunchKernelGGL(k_jacobi, dim3(B), dim3(JAC_THREADS), jsm, st, n, nn, A, Vt, 60, 1e-15, dact);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sort_eig, dim3(1), dim3(256), 0, st, n, A, Vv, eps, C);
+        hipLaunchKernelGGL(k_sort_eig, dim3(B), dim3(256), 0, st, n, nn, A, Vt, eps, C, dact);
         LAUNCH_CHECK();
         return NEGF_OK;
     };
     auto density = [&]() -> int {
-        hipLaunchKernelGGL(k_mu_bisect, dim3(1), dim3(256), 0, st, n, eps, n_spin, beta, dmu, f);
+        hipLaunchKernelGGL(k_mu_bisect, dim3(B), dim3(256), 0, st, n, eps, n_spin, beta, dmu, f, dact);
         LAUNCH_CHECK();
         // rho = C diag(f) C^T
-        return gemm<double>(st, false, true, n, n, n, 1.0, C, n, 0, C, n, 0, 0.0, nullptr, 0, 0, rho, n, 0,
-                            1, f, 0);
+        return gemm<double>(st, false, true, n, n, n, 1.0, C, n, nn, C, n, nn, 0.0, nullptr, 0, 0, rho, n, nn, B, f, n);
     };
 
-    // start: core Hamiltonian
-    hipLaunchKernelGGL(k_core, dim3(grid_for(nn)), dim3(256), 0, st, n, T, v, F);
+    hipLaunchKernelGGL(k_core, g2, dim3(256), 0, st, n, nn, T, v, F);
     LAUNCH_CHECK();
     NEGF_TRY(eig(F, nullptr));
     NEGF_TRY(density());
-    double E_old = INFINITY, E = 0.0, dm = 0.0;
-    int it = 0;
-    bool conv = false;
-    for (it = 1; it <= max_iter; ++it) {
-        hipLaunchKernelGGL(k_fock, dim3(grid_for(nn)), dim3(256), 0, st, n, T, v, V, rho, sigma, F, Sigma0);
+    int it = 0, n_active = B;
+    for (it = 1; it <= max_iter && n_active > 0; ++it) {
+        hipLaunchKernelGGL(k_fock, g2, dim3(256), 0, st, n, nn, T, v, V, rho, sigma, F, Sigma0, dact);
         LAUNCH_CHECK();
-        HIP_TRY(hipMemcpyAsync(Cp, C, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(rho_old, rho, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(Cp, C, sizeof(double) * nn * B, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(rho_old, rho, sizeof(double) * nn * B, hipMemcpyDeviceToDevice, st));
         NEGF_TRY(eig(F, Cp));
         NEGF_TRY(density());
-        hipLaunchKernelGGL(k_hf_energy, dim3(1), dim3(256), 0, st, n, T, v, V, rho, rho_old, sigma, dres);
+        hipLaunchKernelGGL(k_hf_energy, dim3(B), dim3(256), 0, st, n, nn, T, v, V, rho, rho_old, sigma, dres);
         LAUNCH_CHECK();
-        double hres[2];
-        HIP_TRY(hipMemcpyAsync(hres, dres, sizeof(hres), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hres.data(), dres, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        E = hres[0];
-        dm = hres[1];
-        if (!std::isfinite(E)) {
-            set_error("HF energy not finite at iteration %d", it);
-            return NEGF_ENAN;
+        bool changed = false;
+        for (int b = 0; b < B; ++b) {
+            if (!act[b]) continue;
+            E[b] = hres[2 * b];
+            if (!std::isfinite(E[b])) {
+                set_error("HF energy not finite at iteration %d (system %d)", it, b);
+                return NEGF_ENAN;
+            }
+            if (std::fabs(E[b] - E_old[b]) < tol && hres[2 * b + 1] < 10.0 * tol) {
+                act[b] = 0;
+                its[b] = it;
+                --n_active;
+                changed = true;
+            }
+            E_old[b] = E[b];
         }
-        if (std::fabs(E - E_old) < tol && dm < 10.0 * tol) {
-            conv = true;
-            break;
-        }
-        E_old = E;
+        if (changed) HIP_TRY(hipMemcpyAsync(dact, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
     }
-    if (it > max_iter) it = max_iter;
-    double hmu = 0.0;
-    HIP_TRY(hipMemcpyAsync(&hmu, dmu, sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> hmu(B);
+    HIP_TRY(hipMemcpyAsync(hmu.data(), dmu, sizeof(double) * B, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (mu_out) *mu_out = hmu;
-    if (E_out) *E_out = E;
-    if (iters_out) *iters_out = it;
-    if (!conv) {
-        set_error("HF not converged after %d iterations (|dE| tol %g)", max_iter, tol);
+    for (int b = 0; b < B; ++b) {
+        if (mu_out) mu_out[b] = hmu[b];
+        if (E_out) E_out[b] = E[b];
+        if (iters_out) iters_out[b] = its[b];
+    }
+    if (n_active > 0) {
+        set_error("HF not converged after %d iterations for %d system(s) (|dE| tol %g)", max_iter, n_active, tol);
         return NEGF_ENOCONV;
     }
     return NEGF_OK;
+}
+
+int hf_run(negf_ctx* ctx, int n, const double* T, const double* v, const double* V, double n_elec, int sigma,
+           double beta, double tol, int max_iter, double* eps, double* C, double* rho, double* Sigma0, double* mu_out,
+           double* E_out, int* iters_out, hipStream_t st) {
+    return hf_run_batched(ctx, 1, n, T, v, V, n_elec, sigma, beta, tol, max_iter, eps, C, rho, Sigma0, mu_out, E_out,
+                          iters_out, st);
 }
 
 template <class T>

@@ -144,6 +144,44 @@ def test_hf_matches_oracle(he_state):
     assert relerr(host(hfs.Sigma0), o.Sigma0) < TOL64
 
 
+@pytest.mark.parametrize("n_e,n_g,batch", [(7, 5, 5), (6, 4, 3), (1, 2, 2)])
+def test_hf_batched_matches_oracle(ctx, torch_mod, n_e, n_g, batch):
+    """A batch of seeded random potentials on one grid (odd and even n_b, a 1 x 1
+    system): every member against the oracle and against negf_hf alone."""
+    print(f"hf batched n_e={n_e} n_g={n_g} batch={batch}", flush=True)
+    base = W.he_1d(half_width=8.0, n_e=n_e, n_g=n_g, beta=30.0, M=16)
+    systems = [W.random_potential_system(300 + k, base) for k in range(batch)]
+    mats = [negf.fedvr_build_system(s) for s in systems]
+    T = np.stack([m[2] for m in mats]); v = np.stack([m[3] for m in mats]); V = np.stack([m[4] for m in mats])
+    n = v.shape[1]
+    n_elec = 2.0 if n > 1 else 1.0
+    eps, Cm, rho, S0, mu, E, it = negf.hf_batched(ctx, dev(torch_mod, T), dev(torch_mod, v), dev(torch_mod, V),
+                                                   n_elec, 2, base.beta)
+    for b, s in enumerate(systems):
+        st = fedvr.Setup(s)
+        o = H.hartree_fock(st.h, st.V, n_elec, 2, s.beta)
+        assert abs(E[b] - o.E) < TOL64 * abs(o.E), b
+        assert relerr(host(eps[b]), o.eps) < TOL64, b
+        assert abs(mu[b] - o.mu) < 1e-10 * max(1.0, abs(o.mu)), b
+        assert relerr(host(rho[b]), o.rho) < TOL64, b
+        assert relerr(host(S0[b]), o.Sigma0) < TOL64, b
+        # C: orthogonal, and C diag(eps) C^T reproduces the last Fock matrix
+        Cb = host(Cm[b])
+        assert np.max(np.abs(Cb.T @ Cb - np.eye(n))) < 1e-12
+        F = st.h + host(S0[b])
+        assert relerr(Cb @ np.diag(host(eps[b])) @ Cb.T, F) < 1e-12
+        one = negf.hf(ctx, dev(torch_mod, T[b]), dev(torch_mod, v[b]), dev(torch_mod, V[b]), n_elec, 2, s.beta)
+        assert one.iters == it[b]
+        assert abs(one.E - E[b]) < 1e-13 * abs(E[b])
+
+
+def test_hf_batched_rejects_bad_args(ctx, torch_mod):
+    z = torch_mod.zeros((2, 4, 4), dtype=torch_mod.float64, device="cuda")
+    zv = torch_mod.zeros((2, 4), dtype=torch_mod.float64, device="cuda")
+    with pytest.raises(negf.NegfError):
+        negf.hf_batched(ctx, z, zv, z, 9.0, 2, 10.0)  # more electrons than 2 n_b
+
+
 def test_g0_matches_oracle(ctx, he_state):
     s, st, o, hfs = he_state
     tau = negf.tau_grid_system(s)
