@@ -189,6 +189,33 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
  * k-panels. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
+/* Sigma-2B (as negf_sigma2b) for `batch` systems of any sizes n_b[b] on one
+ * tau grid of n_tau points, in a single persistent kernel launch: work items
+ * (system, slice pair, block of rows i) are dealt to per-XCD queues in order of
+ * decreasing n_b, each queue an equal share of the flops, and idle workgroups
+ * steal from the other queues. n_b, sigma (host, batch ints); V, G, Sigma_c
+ * (host arrays of batch device pointers, layouts and element types as
+ * negf_sigma2b for `dtype`). Uses the configuration stored by
+ * negf_sigma2b_batched_tune for this dtype and multiset of n_b, else the
+ * default. Uploads the work list, so it synchronises the stream once.
+ * Errors: NEGF_EINVAL (as negf_sigma2b, per system; n_b beyond the LDS budget
+ * of the configuration). */
+int negf_sigma2b_batched(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
+                         const void* const* V, const void* const* G, void* const* Sigma_c,
+                         int dtype, void* stream);
+
+/* Pin the negf_sigma2b_batched tile configuration (0..5, as negf_sigma2b_set_config)
+ * for this dtype and multiset of n_b (host, batch ints). */
+int negf_sigma2b_batched_set_config(negf_ctx* ctx, int batch, const int* n_b, int dtype, int cfg);
+
+/* Autotuner for negf_sigma2b_batched: times each tile configuration on the
+ * first pair_lim slice pairs of every system (0: all pairs), keeps the fastest
+ * for this dtype and multiset of n_b. Sigma_c is overwritten (partly). *best,
+ * ms[6] (host, nullable) as for negf_sigma2b_tune. Synchronises. */
+int negf_sigma2b_batched_tune(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
+                              const void* const* V, const void* const* G, void* const* Sigma_c,
+                              int dtype, int pair_lim, int* best, double* ms, void* stream);
+
 /* ------------------------------------------------------------------ Dyson */
 typedef struct {
     int kind;                /* NEGF_TAU_UNIFORM or NEGF_TAU_POWER */
@@ -257,6 +284,11 @@ typedef struct {
                                 steps until |dE| < refine_tol (<= 0: tol) */
     double hf_tol;           /* HF stopping rule (<= 0: 1e-13) */
     int hf_max_iter;         /* (<= 0: 1000) */
+    const float* guess_params;   /* dev, nullable: start from the learned guess of this
+                                    network (negf_mlp_guess on G0) instead of G0 */
+    double guess_scale;      /* its output scale */
+    int tune;                /* 1: run the batch tile autotuner first (once per batch shape) */
+    int no_graph;            /* 1: launch every iteration directly (no HIP graphs) */
 } negf_opts_t;
 
 typedef struct {
@@ -283,6 +315,26 @@ int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* opts,
              const double* G_guess, double* G_out, double* E_out, double* N_out,
              int* iters, negf_iter_log_t* log, int log_cap, double* hf_E, double* hf_mu,
              void* stream);
+
+/* The same self-consistent loop for `batch` systems (any n_b, one tau grid:
+ * equal tau_kind, beta, M, u, p) at once. HF runs batched over systems of equal
+ * n_b. Every iteration evaluates Sigma_2B of all unfinished systems in one
+ * persistent kernel launch per arithmetic mode (negf_sigma2b_batched), then
+ * their energies, then their Dyson steps; the two segments are recorded as HIP
+ * graphs and replayed while the set of unfinished systems is unchanged. Each
+ * system stops by its own rule, so its result equals negf_scf on it alone (to
+ * rounding: the tile configuration may differ).
+ * systems (host, batch). G_guess, G_out (host arrays of batch device pointers,
+ * each float64 [n_tau][n_b][n_b]; the arrays and their entries nullable).
+ * E_out, N_out, iters, hf_E, hf_mu, log_n (host, batch entries, nullable).
+ * log (host, nullable): batch x log_cap records, system b from b*log_cap; the
+ * record's ms is the wall time of the whole batch iteration.
+ * Errors: as negf_scf; NEGF_ENOCONV if any system did not converge. Runs on a
+ * stream of its own that first waits for `stream`; returns after it finished. */
+int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* systems,
+                     const negf_opts_t* opts, double* const* G_guess, double* const* G_out,
+                     double* E_out, double* N_out, int* iters, negf_iter_log_t* log, int log_cap,
+                     int* log_n, double* hf_E, double* hf_mu, void* stream);
 
 /* ------------------------------------------------------------------ learned initial guess */
 /* A tau-resolved float32 MLP predicts dG_ij(tau) = G(tau) - G0(tau) of the converged

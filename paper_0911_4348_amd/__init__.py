@@ -60,7 +60,8 @@ class OptsT(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("fixed_iters", C.c_int), ("dtype", C.c_int), ("conv_algo", C.c_int),
                 ("symmetrize", C.c_int), ("refine_tol", C.c_double), ("hf_tol", C.c_double),
-                ("hf_max_iter", C.c_int)]
+                ("hf_max_iter", C.c_int), ("guess_params", C.c_void_p), ("guess_scale", C.c_double),
+                ("tune", C.c_int), ("no_graph", C.c_int)]
 
 
 class IterLogT(C.Structure):
@@ -98,6 +99,12 @@ _SIGS = {
                               _DP, _DP, _VP]),
     "negf_scf": (C.c_int, [_VP, C.POINTER(SystemT), C.POINTER(OptsT), _VP, _VP, _DP, _DP, _IP,
                            C.POINTER(IterLogT), C.c_int, _DP, _DP, _VP]),
+    "negf_scf_batched": (C.c_int, [_VP, C.c_int, C.POINTER(SystemT), C.POINTER(OptsT), _VP, _VP, _DP, _DP, _IP,
+                                   C.POINTER(IterLogT), C.c_int, _IP, _DP, _DP, _VP]),
+    "negf_sigma2b_batched": (C.c_int, [_VP, C.c_int, _IP, C.c_int, _IP, _VP, _VP, _VP, C.c_int, _VP]),
+    "negf_sigma2b_batched_set_config": (C.c_int, [_VP, C.c_int, _IP, C.c_int, C.c_int]),
+    "negf_sigma2b_batched_tune": (C.c_int, [_VP, C.c_int, _IP, C.c_int, _IP, _VP, _VP, _VP, C.c_int, C.c_int,
+                                            _IP, _DP, _VP]),
     "negf_mlp_param_count": (C.c_int, [_IP]),
     "negf_mlp_features": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP, C.c_double,
                                     C.c_int, _VP, _VP, _VP, _VP, _VP]),
@@ -390,29 +397,106 @@ def system_struct(sysd):
     return s, keep
 
 
+def _opts(alpha, tol, max_iter, fixed_iters, dtype, conv, symmetrize, refine_tol, guess=None, guess_scale=1.0,
+          tune=False, graphs=True):
+    return OptsT(float(alpha), float(tol), int(max_iter), int(fixed_iters), _DT[dtype], int(conv),
+                 int(symmetrize), float(refine_tol), 0.0, 0, _dev_ptr(guess), float(guess_scale), int(tune),
+                 0 if graphs else 1)
+
+
+def _records(logs, base, count):
+    return [dict(iter=logs[base + k].iter, dtype=logs[base + k].dtype, E=logs[base + k].E, dE=logs[base + k].dE,
+                 N=logs[base + k].N, ms=logs[base + k].ms) for k in range(count)]
+
+
 def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
         conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
-        allow_noconv=False, stream=None) -> SCFOut:
-    """negf_scf for a workloads.System."""
+        allow_noconv=False, guess=None, guess_scale=1.0, graphs=True, stream=None) -> SCFOut:
+    """negf_scf for a workloads.System (guess: learned-guess parameters on the device)."""
+    out = scf_batched(ctx, [sysd], alpha=alpha, tol=tol, max_iter=max_iter, fixed_iters=fixed_iters, dtype=dtype,
+                      conv=conv, symmetrize=symmetrize, refine_tol=refine_tol,
+                      G_guess=None if G_guess is None else [G_guess], want_G=want_G, allow_noconv=allow_noconv,
+                      guess=guess, guess_scale=guess_scale, graphs=graphs, single=True, stream=stream)
+    return out[0]
+
+
+def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
+                conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
+                allow_noconv=False, guess=None, guess_scale=1.0, tune=False, graphs=True, single=False,
+                stream=None):
+    """negf_scf_batched (single=True: negf_scf) for a list of workloads.System; returns a list of SCFOut."""
     torch = _torch()
-    s, keep = system_struct(sysd)
-    o = OptsT(float(alpha), float(tol), int(max_iter), int(fixed_iters), _DT[dtype], int(conv),
-              int(symmetrize), float(refine_tol), 0.0, 0)
-    n = sysd.n_b
-    n_tau = sysd.n_tau
-    G = torch.empty((n_tau, n, n), dtype=torch.float64, device="cuda") if want_G else None
-    E, N, it, hE, hmu = C.c_double(), C.c_double(), C.c_int(), C.c_double(), C.c_double()
-    cap = max_iter + 2 if not fixed_iters else fixed_iters + 2
-    cap = max(cap, 4) + max_iter
-    logs = (IterLogT * cap)()
-    rc = lib().negf_scf(ctx.handle, C.byref(s), C.byref(o), _dev_ptr(G_guess), _dev_ptr(G), C.byref(E),
-                        C.byref(N), C.byref(it), logs, cap, C.byref(hE), C.byref(hmu), _stream(stream))
+    B = len(systems)
+    keep, structs = [], (SystemT * B)()
+    for b, sd in enumerate(systems):
+        st_, k = system_struct(sd)
+        structs[b] = st_
+        keep.append(k)
+    o = _opts(alpha, tol, max_iter, fixed_iters, dtype, conv, symmetrize, refine_tol, guess, guess_scale, tune,
+              graphs)
+    Gs = [torch.empty((sd.n_tau, sd.n_b, sd.n_b), dtype=torch.float64, device="cuda") if want_G else None
+          for sd in systems]
+    Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
+    guess_p = None
+    if G_guess is not None:
+        guess_p = (C.c_void_p * B)(*[_dev_ptr(g) for g in G_guess])
+    E, N, hE, hmu = np.zeros(B), np.zeros(B), np.zeros(B), np.zeros(B)
+    it, ln = np.zeros(B, dtype=np.int32), np.zeros(B, dtype=np.int32)
+    cap = (fixed_iters if fixed_iters else max_iter) + max_iter + 4
+    logs = (IterLogT * (B * cap))()
+    if single:
+        rc = lib().negf_scf(ctx.handle, C.byref(structs[0]), C.byref(o), guess_p[0] if guess_p else None,
+                            Gp[0], _dptr(E), _dptr(N), it.ctypes.data_as(_IP), logs, cap, _dptr(hE), _dptr(hmu),
+                            _stream(stream))
+        ln[0] = sum(1 for k in range(cap) if logs[k].ms > 0)
+    else:
+        rc = lib().negf_scf_batched(ctx.handle, B, structs, C.byref(o), guess_p, Gp, _dptr(E), _dptr(N),
+                                    it.ctypes.data_as(_IP), logs, cap, ln.ctypes.data_as(_IP), _dptr(hE),
+                                    _dptr(hmu), _stream(stream))
     if rc != OK and not (allow_noconv and rc == ENOCONV):
         _check(rc)
-    rec = [dict(iter=logs[k].iter, dtype=logs[k].dtype, E=logs[k].E, dE=logs[k].dE, N=logs[k].N,
-                ms=logs[k].ms) for k in range(cap) if k == 0 or logs[k].iter != 0]
-    rec = [r for r in rec if r["ms"] > 0]
-    return SCFOut(G, E.value, N.value, it.value, hE.value, hmu.value, rec, rc)
+    return [SCFOut(Gs[b], float(E[b]), float(N[b]), int(it[b]), float(hE[b]), float(hmu[b]),
+                   _records(logs, b * cap, int(ln[b])), rc) for b in range(B)]
+
+
+def sigma2b_batched(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, stream=None):
+    """negf_sigma2b_batched over lists of device tensors V[b] (n_b x n_b), G[b] (n_tau x n_b x n_b)."""
+    torch = _torch()
+    B = len(Gs)
+    if outs is None:
+        outs = [torch.empty_like(g) for g in Gs]
+    n = np.array([g.shape[1] for g in Gs], dtype=np.int32)
+    sg = np.array([sigma] * B if np.isscalar(sigma) else sigma, dtype=np.int32)
+    Vp = (C.c_void_p * B)(*[_dev_ptr(v) for v in Vs])
+    Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
+    Sp = (C.c_void_p * B)(*[_dev_ptr(o) for o in outs])
+    _check(lib().negf_sigma2b_batched(ctx.handle, B, n.ctypes.data_as(_IP), int(Gs[0].shape[0]),
+                                      sg.ctypes.data_as(_IP), Vp, Gp, Sp, _DT[dtype], _stream(stream)))
+    return outs
+
+
+def sigma2b_batched_set_config(ctx: Context, sizes, dtype, cfg):
+    n = np.array(sizes, dtype=np.int32)
+    _check(lib().negf_sigma2b_batched_set_config(ctx.handle, len(n), n.ctypes.data_as(_IP), _DT[dtype], int(cfg)))
+
+
+def sigma2b_batched_tune(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, pair_lim=16, stream=None):
+    """negf_sigma2b_batched_tune: returns (best config, per-config ms)."""
+    torch = _torch()
+    B = len(Gs)
+    if outs is None:
+        outs = [torch.empty_like(g) for g in Gs]
+    n = np.array([g.shape[1] for g in Gs], dtype=np.int32)
+    sg = np.array([sigma] * B if np.isscalar(sigma) else sigma, dtype=np.int32)
+    Vp = (C.c_void_p * B)(*[_dev_ptr(v) for v in Vs])
+    Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
+    Sp = (C.c_void_p * B)(*[_dev_ptr(o) for o in outs])
+    best = C.c_int()
+    ms = np.zeros(6)
+    _check(lib().negf_sigma2b_batched_tune(ctx.handle, B, n.ctypes.data_as(_IP), int(Gs[0].shape[0]),
+                                           sg.ctypes.data_as(_IP), Vp, Gp, Sp, _DT[dtype], int(pair_lim),
+                                           C.byref(best), _dptr(ms), _stream(stream)))
+    return best.value, list(ms)
 
 
 # ------------------------------------------------------------------ learned initial guess

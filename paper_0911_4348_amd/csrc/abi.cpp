@@ -2,6 +2,7 @@
 // tau grids, argument validation, and dispatch to the device code.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -66,6 +67,19 @@ int upload(negf_ctx* c, const char* name, const void* host, size_t bytes, hipStr
     return NEGF_OK;
 }
 
+int upload_cached(negf_ctx* c, const char* name, const void* host, size_t bytes, hipStream_t st, void** out) {
+    auto& prev = c->host_copy[name];
+    const char* h = static_cast<const char*>(host);
+    auto bi = c->bufs.find(name);
+    if (bi != c->bufs.end() && bi->second.p && prev.size() == bytes && std::memcmp(prev.data(), h, bytes) == 0) {
+        *out = bi->second.p;
+        return NEGF_OK;
+    }
+    NEGF_TRY(upload(c, name, host, bytes, st, out));
+    prev.assign(h, h + bytes);
+    return NEGF_OK;
+}
+
 int check_tau_grid(const negf_tau_grid_t* tg) {
     NEGF_REQUIRE(tg != nullptr, "tau grid is NULL");
     NEGF_REQUIRE(tg->tau != nullptr, "tau grid points are NULL");
@@ -121,6 +135,7 @@ extern "C" int negf_ctx_destroy(negf_ctx* c) {
     (void)hipDeviceSynchronize();
     for (auto& kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
+    if (c->work_stream) (void)hipStreamDestroy(c->work_stream);
     if (cur >= 0) (void)hipSetDevice(cur);
     delete c;
     return NEGF_OK;
@@ -396,6 +411,58 @@ extern "C" int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, c
                                     best, ms, st);
     return sigma2b_tune<float>(ctx, n_b, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc,
                                dtype == NEGF_BF16, best, ms, st);
+}
+
+namespace {
+int check_s2b_batch(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma, const void* const* V,
+                    const void* const* G, void* const* Sc, int dtype) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(batch >= 1 && batch <= 65535, "batch = %d out of range [1, 65535]", batch);
+    NEGF_REQUIRE(n_b && sigma && V && G && Sc, "NULL argument array");
+    NEGF_REQUIRE(n_tau >= 2 && n_tau <= (1 << 20), "n_tau = %d out of range", n_tau);
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    for (int b = 0; b < batch; ++b) {
+        NEGF_REQUIRE(n_b[b] >= 1 && n_b[b] <= 4096, "n_b[%d] = %d out of range [1, 4096]", b, n_b[b]);
+        NEGF_REQUIRE(sigma[b] == 1 || sigma[b] == 2, "sigma[%d] must be 1 or 2", b);
+        NEGF_REQUIRE(V[b] && G[b] && Sc[b], "NULL buffer for system %d", b);
+        NEGF_REQUIRE(G[b] != Sc[b], "Sigma_c must not alias G (system %d)", b);
+    }
+    return NEGF_OK;
+}
+}  // namespace
+
+extern "C" int negf_sigma2b_batched(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
+                                    const void* const* V, const void* const* G, void* const* Sc, int dtype,
+                                    void* stream) {
+    NEGF_TRY(check_s2b_batch(ctx, batch, n_b, n_tau, sigma, V, G, Sc, dtype));
+    NEGF_TRY(bind_device(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    S2BBatch pl;
+    NEGF_TRY(s2b_batch_prepare(ctx, "abi", dtype, batch, n_b, n_tau, sigma, V, G, Sc, 0, &pl, st));
+    return s2b_batch_launch(pl, st);
+}
+
+extern "C" int negf_sigma2b_batched_tune(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
+                                         const void* const* V, const void* const* G, void* const* Sc, int dtype,
+                                         int pair_lim, int* best, double* ms, void* stream) {
+    NEGF_TRY(check_s2b_batch(ctx, batch, n_b, n_tau, sigma, V, G, Sc, dtype));
+    NEGF_REQUIRE(pair_lim >= 0, "pair_lim < 0");
+    NEGF_TRY(bind_device(ctx));
+    return s2b_batch_tune(ctx, dtype, batch, n_b, n_tau, sigma, V, G, Sc, pair_lim, best, ms, (hipStream_t)stream);
+}
+
+extern "C" int negf_sigma2b_batched_set_config(negf_ctx* ctx, int batch, const int* n_b, int dtype, int cfg) {
+    NEGF_REQUIRE(ctx && n_b, "NULL argument");
+    NEGF_REQUIRE(batch >= 1 && batch <= 65535, "batch = %d out of range [1, 65535]", batch);
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    NEGF_REQUIRE(cfg >= 0 && cfg < 6, "tile configuration %d out of range [0, 6)", cfg);
+    for (int b = 0; b < batch; ++b) NEGF_REQUIRE(n_b[b] >= 1 && n_b[b] <= 4096, "n_b[%d] out of range", b);
+    std::vector<int> ns(n_b, n_b + batch);
+    std::sort(ns.begin(), ns.end());
+    std::string key = "s2bB_" + std::to_string(dtype == NEGF_F64 ? 0 : (dtype == NEGF_BF16 ? 2 : 1));
+    for (int v : ns) key += "_" + std::to_string(v);
+    ctx->filled[key] = cfg;
+    return NEGF_OK;
 }
 
 extern "C" int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg) {

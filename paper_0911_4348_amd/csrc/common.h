@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <map>
+#include <vector>
 #include <string>
 
 #include "negf.h"
@@ -25,7 +26,9 @@ struct negf_ctx {
     int device = 0;
     std::map<std::string, negf::Buf> bufs;   // named, grow-only scratch
     std::map<std::string, int> filled;       // constant tables already uploaded
+    std::map<std::string, std::vector<char>> host_copy;   // contents of cached uploads
     size_t total = 0;
+    hipStream_t work_stream = nullptr;        // stream of the SCF driver (graph capture needs one)
 };
 
 namespace negf {
@@ -42,6 +45,8 @@ inline int scratch_t(negf_ctx* c, const char* name, size_t count, T** out) {
 int bind_device(negf_ctx* c);
 // Copy a small host table into named scratch and wait for the copy.
 int upload(negf_ctx* c, const char* name, const void* host, size_t bytes, hipStream_t st, void** out);
+// As upload, but skipped (no copy, no wait) when the buffer already holds these bytes.
+int upload_cached(negf_ctx* c, const char* name, const void* host, size_t bytes, hipStream_t st, void** out);
 
 // ---------------------------------------------------------------- GEMM
 // C[b] = alpha * op(A[b]) diag(s[b]) op(B[b]) + beta * Cin[b] for b < batch.
@@ -55,6 +60,26 @@ int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha,
          int batch, const T* colscale = nullptr, long sS = 0);
 
 // ---------------------------------------------------------------- HF pieces
+// Work list of the persistent Sigma-2B kernel for a batch of systems.
+struct S2BBatch {
+    int mode = 0, cfg = -1, n_cu = 0;
+    int n_inst = 0, n_tau = 0, max_n = 0;
+    long n_items = 0;
+    std::vector<long> cuts;              // 9 item offsets: the per-XCD queues
+    void* d_inst = nullptr;              // device descriptors (systems by decreasing n_b)
+    int* heads = nullptr;                // 8 queue counters
+    std::vector<int> n_sorted;
+    std::vector<const void*> G_sorted;
+    std::vector<int*> ex_sorted;
+    std::string key;                     // tuner cache key (mode and multiset of n_b)
+};
+int s2b_batch_prepare(negf_ctx* ctx, const char* tag, int dtype, int batch, const int* n, int n_tau,
+                      const int* sigma, const void* const* V, const void* const* G, void* const* Sc, int pair_lim,
+                      S2BBatch* plan, hipStream_t st);
+int s2b_batch_launch(const S2BBatch& plan, hipStream_t st);
+int s2b_batch_tune(negf_ctx* ctx, int dtype, int batch, const int* n, int n_tau, const int* sigma,
+                   const void* const* V, const void* const* G, void* const* Sc, int pair_lim, int* best, double* ms,
+                   hipStream_t st);
 int hf_run_batched(negf_ctx* ctx, int B, int n_b, const double* T, const double* v, const double* V,
                    double n_elec, int sigma, double beta, double tol, int max_iter, double* eps, double* C,
                    double* rho, double* Sigma0, double* mu, double* E_hf, int* iters, hipStream_t st);
@@ -81,6 +106,9 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, cons
               const double* V, const double* eps, const double* C, double mu,
               const double* Sigma0, const T* G_in, const T* Sc, double alpha, int symmetrize,
               int conv_algo, T* G_out, hipStream_t st);
+template <class T>
+int energy_launch(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, const double* h,
+                  const double* V, const T* G, const T* Sc, double* out, hipStream_t st);
 template <class T>
 int energy_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, const double* h,
                const double* V, const T* G, const T* Sc, double* E, double* N, hipStream_t st);

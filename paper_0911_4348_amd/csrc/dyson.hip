@@ -552,7 +552,7 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
         tabs[3 * n_tau + q] = hR[q];
     }
     void* dtab = nullptr;
-    NEGF_TRY(upload(ctx, "dy_grid", tabs.data(), sizeof(double) * tabs.size(), st, &dtab));
+    NEGF_TRY(upload_cached(ctx, "dy_grid", tabs.data(), sizeof(double) * tabs.size(), st, &dtab));
     const double* d_tau = (const double*)dtab;
     const double* d_w = d_tau + n_tau;
     const double* d_hL = d_tau + 2 * n_tau;
@@ -639,22 +639,32 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
     return NEGF_OK;
 }
 
+// Galitskii-Migdal energy and particle number of G into out[0], out[1] (device);
+// stream-ordered, no host synchronisation once the weights are on the device.
 template <class T>
-int energy_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const double* h, const double* V,
-               const T* G, const T* Sc, double* E, double* N, hipStream_t st) {
+int energy_launch(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const double* h, const double* V,
+                  const T* G, const T* Sc, double* out, hipStream_t st) {
     const int n_tau = tg->n_tau;
     std::vector<double> w, hL, hR;
     grid_tables(tg, w, hL, hR);
     void* dw = nullptr;
-    NEGF_TRY(upload(ctx, "en_w", w.data(), sizeof(double) * n_tau, st, &dw));
-    double *part, *out;
+    NEGF_TRY(upload_cached(ctx, "en_w", w.data(), sizeof(double) * n_tau, st, &dw));
+    double* part;
     NEGF_TRY(scratch_t(ctx, "en_part", n_tau, &part));
-    NEGF_TRY(scratch_t(ctx, "en_out", 2, &out));
     hipLaunchKernelGGL((k_energy_slices<T>), dim3(n_tau), dim3(256), 0, st, n, n_tau, Sc, G, part);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_energy_final<T>), dim3(1), dim3(256), 0, st, n, n_tau, sigma, h, V,
                        G + (long)(n_tau - 1) * n * n, (const double*)dw, part, out);
     LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+template <class T>
+int energy_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const double* h, const double* V,
+               const T* G, const T* Sc, double* E, double* N, hipStream_t st) {
+    double* out;
+    NEGF_TRY(scratch_t(ctx, "en_out", 2, &out));
+    NEGF_TRY(energy_launch<T>(ctx, tg, n, sigma, h, V, G, Sc, out, st));
     double hres[2];
     HIP_TRY(hipMemcpyAsync(hres, out, sizeof(hres), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -669,6 +679,10 @@ template int dyson_run<double>(negf_ctx*, const negf_tau_grid_t*, int, int, cons
 template int dyson_run<float>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
                               const double*, const double*, double, const double*, const float*, const float*,
                               double, int, int, float*, hipStream_t);
+template int energy_launch<double>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
+                                   const double*, const double*, double*, hipStream_t);
+template int energy_launch<float>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
+                                  const float*, const float*, double*, hipStream_t);
 template int energy_run<double>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
                                 const double*, const double*, double*, double*, hipStream_t);
 template int energy_run<float>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,

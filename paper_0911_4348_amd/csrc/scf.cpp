@@ -1,181 +1,483 @@
 // Self-consistent second-Born ground state (paper Sec. 2.3): FE-DVR setup,
-// HF, then Sigma_2B / energy / Dyson step until the energy settles.
+// HF, then Sigma_2B / energy / Dyson step until the energy settles, for one
+// system or a batch of systems of different sizes on one tau grid.
 //
-// Loop (k = 0, 1, ...): Sigma_c = Sigma_2B[G_k]; E_k = E_GM[G_k, Sigma_c];
-// stop if k >= 1 and |E_k - E_(k-1)| < tol; else G_(k+1) = Dyson step of G_k.
-// The mixed form runs this loop in float32 (Sigma_2B optionally on bf16
+// Loop (k = 0, 1, ...), per system: Sigma_c = Sigma_2B[G_k]; E_k = E_GM[G_k,
+// Sigma_c]; stop if k >= 1 and |E_k - E_(k-1)| < tol; else G_(k+1) = Dyson step
+// of G_k. The mixed form runs this loop in float32 (Sigma_2B optionally on bf16
 // matrix cores) and then continues in float64 from the float32 fixed point
 // until the float64 energy settles; energies, the HF step and the chemical
 // potential are always float64.
+//
+// Batch execution: one iteration of all unfinished systems is two stream
+// segments, (a) Sigma_2B of every system in one persistent kernel launch per
+// arithmetic mode plus every energy, (b) every Dyson step. The energies are
+// read back between them (the only host synchronisation per iteration). Each
+// segment is recorded once as a HIP graph and replayed while the set of
+// unfinished systems does not change; a new set is first run directly (it may
+// grow scratch buffers) and recorded at its second iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "common.h"
 
 using namespace negf;
 
+extern "C" int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
+                              const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,
+                              const double* tau, double beta, const double* G0, double* G_out, void* stream);
+
 namespace {
 
-struct Iterate {
-    int k;
-    double E, N;
+enum { PH_LOW = 0, PH_F64 = 1, PH_DONE = 2 };
+
+struct Sys {
+    int b;                   // index in the caller's arrays
+    int n;
+    long nn;
+    double *T, *v, *V, *h, *x;          // device, float64
+    double *eps, *C, *rho, *Sig0;       // HF state
+    double mu = 0, Ehf = 0;
+    int hf_it = 0;
+    double* G = nullptr;     // float64 iterate
+    double* Sc = nullptr;
+    float *Gf = nullptr, *Scf = nullptr, *Vf = nullptr;
+    int phase = PH_F64;
+    int k = 0;               // Sigma/energy evaluations done in this phase, minus one
+    int limit = 0;
+    int steps_low = 0;
+    double E_prev = NAN, E = 0, N = 0;
+    bool conv = false;
+    int log_n = 0;
 };
 
-template <class T>
-int scf_phase(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const double* h, const double* V64,
-              const T* Vt, const double* eps, const double* C, double mu, const double* Sigma0, T* G, T* Sc,
-              double alpha, int symmetrize, int conv_algo, int sig_dtype, double tol, int limit, bool fixed,
-              int dtype_tag, double e_nn, int* steps_done, double* E_last, double* N_last, bool* converged,
-              negf_iter_log_t* log, int log_cap, int* log_n, int step_offset, hipStream_t st) {
-    const int n_tau = tg->n_tau;
-    const int dt = sizeof(T) == 8 ? NEGF_F64 : NEGF_F32;
-    double E_prev = NAN;
-    int k = 0;
-    *converged = false;
-    while (true) {
-        auto t0 = std::chrono::steady_clock::now();
-        NEGF_TRY(negf_sigma2b(ctx, n, n_tau, sigma, Vt, G, Sc, sig_dtype, st));
-        double E = 0, N = 0;
-        NEGF_TRY(energy_run<T>(ctx, tg, n, sigma, h, V64, G, Sc, &E, &N, st));
-        E += e_nn;
-        if (!std::isfinite(E) || !std::isfinite(N)) {
-            set_error("energy or particle number not finite at step %d", step_offset + k);
-            *E_last = E;
-            *N_last = N;
-            *steps_done = k;
-            return NEGF_ENAN;
-        }
-        const double dE = std::isnan(E_prev) ? NAN : E - E_prev;
-        bool stop = false;
-        if (!fixed && k >= 1 && std::fabs(dE) < tol) {
-            *converged = true;
-            stop = true;
-        }
-        if (k >= limit) stop = true;
-        if (!stop) NEGF_TRY(dyson_run<T>(ctx, tg, n, sigma, h, V64, eps, C, mu, Sigma0, G, Sc, alpha, symmetrize,
-                                         conv_algo, G, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        if (log && *log_n < log_cap) log[(*log_n)++] = negf_iter_log_t{step_offset + k, dtype_tag, E, dE, N, ms};
-        *E_last = E;
-        *N_last = N;
-        if (stop) break;
-        E_prev = E;
-        ++k;
+struct GraphSlot {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    bool seen = false;       // key already run once directly
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
     }
-    *steps_done = k;
-    (void)dt;
+};
+
+// Run `body` on stream st: directly, or recorded into slot's graph and replayed.
+template <class F>
+int run_segment(GraphSlot& slot, const std::string& key, bool graphs, GraphSlot& other, hipStream_t st, F body) {
+    if (!graphs) return body();
+    if (key != slot.key) {
+        // new set of systems: run directly once (scratch may grow, which
+        // invalidates every recorded graph)
+        slot.drop();
+        other.drop();
+        slot.key = key;
+        slot.seen = true;
+        return body();
+    }
+    if (!slot.exec) {
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        const int rc = body();
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc != NEGF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(e));
+            return NEGF_EHIP;
+        }
+        const hipError_t e2 = hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            slot.exec = nullptr;
+            set_error("graph instantiation failed: %s", hipGetErrorString(e2));
+            return NEGF_EHIP;
+        }
+    }
+    HIP_TRY(hipGraphLaunch(slot.exec, st));
+    return NEGF_OK;
+}
+
+int validate(const negf_system_t* s, int* n, int* n_tau) {
+    NEGF_REQUIRE(s->sigma == 1 || s->sigma == 2, "sigma must be 1 or 2");
+    NEGF_REQUIRE(s->beta > 0 && std::isfinite(s->beta), "beta must be positive");
+    NEGF_TRY(negf_fedvr_size(s->grid.n_e, s->grid.n_g, n));
+    NEGF_REQUIRE(*n <= 4096, "n_b too large");
+    NEGF_REQUIRE(s->n_elec > 0 && s->n_elec < (double)s->sigma * *n, "n_elec out of range");
+    NEGF_TRY(negf_tau_count(s->tau_kind, s->M, s->u, s->p, n_tau));
     return NEGF_OK;
 }
 
 }  // namespace
 
-extern "C" int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* o, const double* G_guess,
-                        double* G_out, double* E_out, double* N_out, int* iters, negf_iter_log_t* log, int log_cap,
-                        double* hf_E, double* hf_mu, void* stream) {
-    NEGF_REQUIRE(ctx && sys && o, "NULL argument");
+extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* systems, const negf_opts_t* o,
+                                double* const* G_guess, double* const* G_out, double* E_out, double* N_out,
+                                int* iters, negf_iter_log_t* log, int log_cap, int* log_n, double* hf_E,
+                                double* hf_mu, void* stream) {
+    NEGF_REQUIRE(ctx && systems && o, "NULL argument");
+    NEGF_REQUIRE(batch >= 1 && batch <= 4096, "batch = %d out of range [1, 4096]", batch);
     NEGF_REQUIRE(o->alpha > 0 && o->alpha <= 1, "alpha must be in (0, 1]");
     NEGF_REQUIRE(o->tol > 0, "tol must be positive");
     NEGF_REQUIRE(o->max_iter >= 1 || o->fixed_iters > 0, "max_iter must be >= 1");
     NEGF_REQUIRE(o->dtype == NEGF_F64 || o->dtype == NEGF_F32 || o->dtype == NEGF_BF16, "bad dtype");
     NEGF_REQUIRE(o->conv_algo >= NEGF_CONV_AUTO && o->conv_algo <= NEGF_CONV_DIRECT, "bad conv_algo");
-    NEGF_REQUIRE(sys->sigma == 1 || sys->sigma == 2, "sigma must be 1 or 2");
-    NEGF_REQUIRE(sys->beta > 0 && std::isfinite(sys->beta), "beta must be positive");
     NEGF_REQUIRE(log_cap >= 0, "log_cap < 0");
-    int n = 0, n_tau = 0;
-    NEGF_TRY(negf_fedvr_size(sys->grid.n_e, sys->grid.n_g, &n));
-    NEGF_REQUIRE(n <= 4096, "n_b too large");
-    NEGF_REQUIRE(sys->n_elec > 0 && sys->n_elec < (double)sys->sigma * n, "n_elec out of range");
-    NEGF_TRY(negf_tau_count(sys->tau_kind, sys->M, sys->u, sys->p, &n_tau));
+    NEGF_REQUIRE(!o->guess_params || !G_guess, "give either G_guess or guess_params, not both");
+    const negf_system_t& s0 = systems[0];
+    int n_tau = 0;
+    std::vector<int> nb(batch);
+    for (int b = 0; b < batch; ++b) {
+        const negf_system_t& s = systems[b];
+        int nt = 0;
+        NEGF_TRY(validate(&s, &nb[b], &nt));
+        NEGF_REQUIRE(s.tau_kind == s0.tau_kind && s.beta == s0.beta && s.M == s0.M && s.u == s0.u && s.p == s0.p,
+                     "system %d: every system of a batch must use the same tau grid", b);
+        if (o->guess_params) NEGF_REQUIRE(s.pot.n_c <= 3, "the learned guess takes at most 3 nuclei");
+        n_tau = nt;
+    }
     std::vector<double> tau(n_tau);
-    NEGF_TRY(negf_tau_grid(sys->tau_kind, sys->beta, sys->M, sys->u, sys->p, tau.data()));
-    negf_tau_grid_t tg{sys->tau_kind, n_tau, sys->tau_kind == NEGF_TAU_POWER ? sys->u : 0, sys->beta, tau.data()};
+    NEGF_TRY(negf_tau_grid(s0.tau_kind, s0.beta, s0.M, s0.u, s0.p, tau.data()));
+    negf_tau_grid_t tg{s0.tau_kind, n_tau, s0.tau_kind == NEGF_TAU_POWER ? s0.u : 0, s0.beta, tau.data()};
     NEGF_TRY(check_tau_grid(&tg));
     if (o->conv_algo == NEGF_CONV_FFT) {
         const int M = n_tau - 1;
-        NEGF_REQUIRE(sys->tau_kind == NEGF_TAU_UNIFORM && (M & (M - 1)) == 0 && M <= 8192,
+        NEGF_REQUIRE(s0.tau_kind == NEGF_TAU_UNIFORM && (M & (M - 1)) == 0 && M <= 8192,
                      "the Fourier route needs a uniform grid with a power-of-two M <= 8192");
     }
-    const long nn = (long)n * n;
-    std::vector<double> T((size_t)nn), v(n), V((size_t)nn), h((size_t)nn);
-    NEGF_TRY(fedvr_build(&sys->grid, &sys->pot, nullptr, nullptr, T.data(), v.data(), V.data()));
-    for (long e = 0; e < nn; ++e) h[e] = T[e] + ((e / n) == (e % n) ? v[e / n] : 0.0);
     NEGF_TRY(bind_device(ctx));
-    hipStream_t st = (hipStream_t)stream;
+    if (!ctx->work_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
+    hipStream_t st = ctx->work_stream;
+    {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev, (hipStream_t)stream));
+        HIP_TRY(hipStreamWaitEvent(st, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
 
-    void *dT, *dv, *dV, *dh;
-    NEGF_TRY(upload(ctx, "scf_T", T.data(), sizeof(double) * nn, st, &dT));
-    NEGF_TRY(upload(ctx, "scf_v", v.data(), sizeof(double) * n, st, &dv));
-    NEGF_TRY(upload(ctx, "scf_V", V.data(), sizeof(double) * nn, st, &dV));
-    NEGF_TRY(upload(ctx, "scf_h", h.data(), sizeof(double) * nn, st, &dh));
-    double *eps, *C, *rho, *Sig0;
-    NEGF_TRY(scratch_t(ctx, "scf_eps", n, &eps));
-    NEGF_TRY(scratch_t(ctx, "scf_C", nn, &C));
-    NEGF_TRY(scratch_t(ctx, "scf_rho", nn, &rho));
-    NEGF_TRY(scratch_t(ctx, "scf_Sig0", nn, &Sig0));
-    double mu = 0, Ehf = 0;
-    int hf_it = 0;
-    const double hf_tol = o->hf_tol > 0 ? o->hf_tol : 1e-13;
-    const int hf_max = o->hf_max_iter > 0 ? o->hf_max_iter : 1000;
-    NEGF_TRY(hf_run(ctx, n, (double*)dT, (double*)dv, (double*)dV, sys->n_elec, sys->sigma, sys->beta, hf_tol, hf_max,
-                    eps, C, rho, Sig0, &mu, &Ehf, &hf_it, st));
-    if (hf_E) *hf_E = Ehf + sys->e_nn;
-    if (hf_mu) *hf_mu = mu;
-
-    double *G, *Sc;
-    NEGF_TRY(scratch_t(ctx, "scf_G", nn * n_tau, &G));
-    NEGF_TRY(scratch_t(ctx, "scf_Sc", nn * n_tau, &Sc));
-    if (G_guess) HIP_TRY(hipMemcpyAsync(G, G_guess, sizeof(double) * nn * n_tau, hipMemcpyDeviceToDevice, st));
-    else NEGF_TRY(g0_build<double>(ctx, n, n_tau, tau.data(), sys->beta, eps, C, mu, G, st));
-
-    const bool fixed = o->fixed_iters > 0;
-    const int limit = fixed ? o->fixed_iters : o->max_iter;
-    int log_n = 0, steps = 0, total = 0;
-    double E = 0, N = 0;
-    bool conv = false;
-    int rc = NEGF_OK;
-    if (o->dtype == NEGF_F64) {
-        rc = scf_phase<double>(ctx, &tg, n, sys->sigma, (double*)dh, (double*)dV, (double*)dV, eps, C, mu, Sig0, G, Sc,
-                               o->alpha, o->symmetrize, o->conv_algo, NEGF_F64, o->tol, limit, fixed, NEGF_F64,
-                               sys->e_nn, &steps, &E, &N, &conv, log, log_cap, &log_n, 0, st);
-        total = steps;
-    } else {
-        float *Gf, *Scf, *Vf;
-        NEGF_TRY(scratch_t(ctx, "scf_Gf", nn * n_tau, &Gf));
-        NEGF_TRY(scratch_t(ctx, "scf_Scf", nn * n_tau, &Scf));
-        NEGF_TRY(scratch_t(ctx, "scf_Vf", nn, &Vf));
-        NEGF_TRY(to_f32(G, Gf, nn * n_tau, st));
-        NEGF_TRY(to_f32((double*)dV, Vf, nn, st));
-        rc = scf_phase<float>(ctx, &tg, n, sys->sigma, (double*)dh, (double*)dV, Vf, eps, C, mu, Sig0, Gf, Scf, o->alpha,
-                              o->symmetrize, o->conv_algo, o->dtype, o->tol, limit, fixed, o->dtype, sys->e_nn, &steps,
-                              &E, &N, &conv, log, log_cap, &log_n, 0, st);
-        total = steps;
-        if (rc == NEGF_OK && !fixed) {
-            // float64 refinement starting from the low-precision fixed point
-            NEGF_TRY((convert<double, float>(Gf, G, nn * n_tau, st)));
-            const double rt = o->refine_tol > 0 ? o->refine_tol : o->tol;
-            int s2 = 0;
-            rc = scf_phase<double>(ctx, &tg, n, sys->sigma, (double*)dh, (double*)dV, (double*)dV, eps, C, mu, Sig0, G,
-                                   Sc, o->alpha, o->symmetrize, o->conv_algo, NEGF_F64, rt,
-                                   o->max_iter > steps ? o->max_iter - steps : 1, false, NEGF_F64, sys->e_nn, &s2, &E,
-                                   &N, &conv, log, log_cap, &log_n, steps, st);
-            total = steps + s2;
-        } else if (rc == NEGF_OK) {
-            NEGF_TRY((convert<double, float>(Gf, G, nn * n_tau, st)));
+    // ---------------- setup: systems by decreasing n_b, matrices stacked in that order
+    std::vector<int> order(batch);
+    for (int b = 0; b < batch; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nb[a] > nb[c]; });
+    std::vector<Sys> S(batch);
+    long tot_nn = 0, tot_n = 0, tot_g = 0;
+    for (int r = 0; r < batch; ++r) {
+        S[r].b = order[r];
+        S[r].n = nb[order[r]];
+        S[r].nn = (long)S[r].n * S[r].n;
+        tot_nn += S[r].nn;
+        tot_n += S[r].n;
+        if (!(G_out && G_out[order[r]])) tot_g += S[r].nn * n_tau;
+    }
+    std::vector<double> hT(tot_nn), hv(tot_n), hV(tot_nn), hh(tot_nn), hx(tot_n);
+    {
+        long om = 0, ov = 0;
+        for (int r = 0; r < batch; ++r) {
+            const negf_system_t& s = systems[S[r].b];
+            const int n = S[r].n;
+            NEGF_TRY(fedvr_build(&s.grid, &s.pot, hx.data() + ov, nullptr, hT.data() + om, hv.data() + ov,
+                                 hV.data() + om));
+            for (long e = 0; e < S[r].nn; ++e)
+                hh[om + e] = hT[om + e] + ((e / n) == (e % n) ? hv[ov + e / n] : 0.0);
+            om += S[r].nn;
+            ov += n;
         }
     }
-    if (G_out) HIP_TRY(hipMemcpyAsync(G_out, G, sizeof(double) * nn * n_tau, hipMemcpyDeviceToDevice, st));
+    void *dT, *dv, *dV, *dh, *dx, *dtau;
+    NEGF_TRY(upload(ctx, "scf_T", hT.data(), sizeof(double) * tot_nn, st, &dT));
+    NEGF_TRY(upload(ctx, "scf_v", hv.data(), sizeof(double) * tot_n, st, &dv));
+    NEGF_TRY(upload(ctx, "scf_V", hV.data(), sizeof(double) * tot_nn, st, &dV));
+    NEGF_TRY(upload(ctx, "scf_h", hh.data(), sizeof(double) * tot_nn, st, &dh));
+    NEGF_TRY(upload(ctx, "scf_x", hx.data(), sizeof(double) * tot_n, st, &dx));
+    NEGF_TRY(upload_cached(ctx, "scf_tau", tau.data(), sizeof(double) * n_tau, st, &dtau));
+    double *eps, *C, *rho, *Sig0, *Sc, *Gint = nullptr;
+    NEGF_TRY(scratch_t(ctx, "scf_eps", tot_n, &eps));
+    NEGF_TRY(scratch_t(ctx, "scf_C", tot_nn, &C));
+    NEGF_TRY(scratch_t(ctx, "scf_rho", tot_nn, &rho));
+    NEGF_TRY(scratch_t(ctx, "scf_Sig0", tot_nn, &Sig0));
+    NEGF_TRY(scratch_t(ctx, "scf_Sc", tot_nn * n_tau, &Sc));
+    if (tot_g) NEGF_TRY(scratch_t(ctx, "scf_G", tot_g, &Gint));
+    const bool low = o->dtype != NEGF_F64;
+    float *Gf = nullptr, *Scf = nullptr, *Vf = nullptr;
+    if (low) {
+        NEGF_TRY(scratch_t(ctx, "scf_Gf", tot_nn * n_tau, &Gf));
+        NEGF_TRY(scratch_t(ctx, "scf_Scf", tot_nn * n_tau, &Scf));
+        NEGF_TRY(scratch_t(ctx, "scf_Vf", tot_nn, &Vf));
+    }
+    {
+        long om = 0, ov = 0, og = 0;
+        for (int r = 0; r < batch; ++r) {
+            Sys& y = S[r];
+            y.T = (double*)dT + om;
+            y.V = (double*)dV + om;
+            y.h = (double*)dh + om;
+            y.v = (double*)dv + ov;
+            y.x = (double*)dx + ov;
+            y.eps = eps + ov;
+            y.C = C + om;
+            y.rho = rho + om;
+            y.Sig0 = Sig0 + om;
+            y.Sc = Sc + om * n_tau;
+            if (G_out && G_out[y.b]) {
+                y.G = G_out[y.b];
+            } else {
+                y.G = Gint + og;
+                og += y.nn * n_tau;
+            }
+            if (low) {
+                y.Gf = Gf + om * n_tau;
+                y.Scf = Scf + om * n_tau;
+                y.Vf = Vf + om;
+            }
+            om += y.nn;
+            ov += y.n;
+        }
+    }
+
+    // ---------------- HF, one batched solve per group of equal n_b
+    const double hf_tol = o->hf_tol > 0 ? o->hf_tol : 1e-13;
+    const int hf_max = o->hf_max_iter > 0 ? o->hf_max_iter : 1000;
+    for (int r0 = 0; r0 < batch;) {
+        int r1 = r0;
+        while (r1 < batch && S[r1].n == S[r0].n && systems[S[r1].b].n_elec == systems[S[r0].b].n_elec &&
+               systems[S[r1].b].sigma == systems[S[r0].b].sigma)
+            ++r1;
+        const int B = r1 - r0;
+        std::vector<double> mu(B), E(B);
+        std::vector<int> it(B);
+        const negf_system_t& sg = systems[S[r0].b];
+        NEGF_TRY(hf_run_batched(ctx, B, S[r0].n, S[r0].T, S[r0].v, S[r0].V, sg.n_elec, sg.sigma, sg.beta, hf_tol,
+                                hf_max, S[r0].eps, S[r0].C, S[r0].rho, S[r0].Sig0, mu.data(), E.data(), it.data(),
+                                st));
+        for (int r = r0; r < r1; ++r) {
+            S[r].mu = mu[r - r0];
+            S[r].Ehf = E[r - r0];
+            S[r].hf_it = it[r - r0];
+            if (hf_E) hf_E[S[r].b] = S[r].Ehf + systems[S[r].b].e_nn;
+            if (hf_mu) hf_mu[S[r].b] = S[r].mu;
+        }
+        r0 = r1;
+    }
+
+    // ---------------- starting G
+    for (Sys& y : S) {
+        const negf_system_t& s = systems[y.b];
+        if (G_guess && G_guess[y.b]) {
+            HIP_TRY(hipMemcpyAsync(y.G, G_guess[y.b], sizeof(double) * y.nn * n_tau, hipMemcpyDeviceToDevice, st));
+        } else {
+            NEGF_TRY(g0_build<double>(ctx, y.n, n_tau, tau.data(), s.beta, y.eps, y.C, y.mu, y.G, st));
+            if (o->guess_params)
+                NEGF_TRY(negf_mlp_guess(ctx, o->guess_params, o->guess_scale, y.n, y.x, y.v, s.pot.n_c, s.pot.X,
+                                        s.pot.Z, n_tau, (const double*)dtau, s.beta, y.G, y.G, st));
+        }
+        if (low) {
+            NEGF_TRY(to_f32(y.G, y.Gf, y.nn * n_tau, st));
+            NEGF_TRY(to_f32(y.V, y.Vf, y.nn, st));
+        }
+    }
+
+    // ---------------- iteration
+    const bool fixed = o->fixed_iters > 0;
+    for (Sys& y : S) {
+        y.phase = low ? PH_LOW : PH_F64;
+        y.limit = fixed ? o->fixed_iters : o->max_iter;
+    }
+    if (o->tune) {
+        // tile autotuner for each arithmetic mode over the whole batch (first 16 slice pairs)
+        for (int pass = 0; pass < (low ? 2 : 1); ++pass) {
+            const int dt = pass == 0 ? o->dtype : NEGF_F64;
+            std::vector<int> n(batch), sg(batch);
+            std::vector<const void*> Vp(batch), Gp(batch);
+            std::vector<void*> Sp(batch);
+            for (int r = 0; r < batch; ++r) {
+                n[r] = S[r].n;
+                sg[r] = systems[S[r].b].sigma;
+                const bool f = dt != NEGF_F64;
+                Vp[r] = f ? (const void*)S[r].Vf : (const void*)S[r].V;
+                Gp[r] = f ? (const void*)S[r].Gf : (const void*)S[r].G;
+                Sp[r] = f ? (void*)S[r].Scf : (void*)S[r].Sc;
+            }
+            S2BBatch probe;
+            NEGF_TRY(s2b_batch_prepare(ctx, "probe", dt, batch, n.data(), n_tau, sg.data(), Vp.data(), Gp.data(),
+                                       Sp.data(), 16, &probe, st));
+            if (!ctx->filled.count(probe.key))
+                NEGF_TRY(s2b_batch_tune(ctx, dt, batch, n.data(), n_tau, sg.data(), Vp.data(), Gp.data(), Sp.data(),
+                                        16, nullptr, nullptr, st));
+        }
+    }
+
+    double* dEN;
+    NEGF_TRY(scratch_t(ctx, "scf_EN", 2 * (size_t)batch, &dEN));
+    std::vector<double> hEN(2 * (size_t)batch);
+    const bool graphs = !o->no_graph;
+    GraphSlot gS, gD;
+    S2BBatch plan_lo, plan_hi;
+    std::string plan_key;
+    int rc = NEGF_OK;
+    auto t_prev = std::chrono::steady_clock::now();
+    while (true) {
+        std::vector<int> act_lo, act_hi;
+        for (int r = 0; r < batch; ++r) {
+            if (S[r].phase == PH_LOW) act_lo.push_back(r);
+            else if (S[r].phase == PH_F64) act_hi.push_back(r);
+        }
+        if (act_lo.empty() && act_hi.empty()) break;
+        std::string keyS = "S";
+        for (int r : act_lo) keyS += " l" + std::to_string(r);
+        for (int r : act_hi) keyS += " h" + std::to_string(r);
+        if (keyS != plan_key) {
+            // work lists of the persistent Sigma-2B launches (uploads: outside any graph)
+            auto prep = [&](const std::vector<int>& rs, int dt, const char* tag, S2BBatch* pl) -> int {
+                *pl = S2BBatch();
+                if (rs.empty()) return NEGF_OK;
+                const int B = (int)rs.size();
+                std::vector<int> n(B), sg(B);
+                std::vector<const void*> Vp(B), Gp(B);
+                std::vector<void*> Sp(B);
+                for (int i = 0; i < B; ++i) {
+                    const Sys& y = S[rs[i]];
+                    n[i] = y.n;
+                    sg[i] = systems[y.b].sigma;
+                    const bool f = dt != NEGF_F64;
+                    Vp[i] = f ? (const void*)y.Vf : (const void*)y.V;
+                    Gp[i] = f ? (const void*)y.Gf : (const void*)y.G;
+                    Sp[i] = f ? (void*)y.Scf : (void*)y.Sc;
+                }
+                return s2b_batch_prepare(ctx, tag, dt, B, n.data(), n_tau, sg.data(), Vp.data(), Gp.data(),
+                                         Sp.data(), 0, pl, st);
+            };
+            NEGF_TRY(prep(act_lo, o->dtype, "lo", &plan_lo));
+            NEGF_TRY(prep(act_hi, NEGF_F64, "hi", &plan_hi));
+            plan_key = keyS;
+            gS.drop();
+            gD.drop();
+            gS.key.clear();
+            gD.key.clear();
+        }
+        // (a) Sigma_2B of every unfinished system, then every energy
+        NEGF_TRY(run_segment(gS, keyS, graphs, gD, st, [&]() -> int {
+            if (!act_lo.empty()) NEGF_TRY(s2b_batch_launch(plan_lo, st));
+            if (!act_hi.empty()) NEGF_TRY(s2b_batch_launch(plan_hi, st));
+            for (int r : act_lo) {
+                const Sys& y = S[r];
+                NEGF_TRY(energy_launch<float>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.Gf, y.Scf,
+                                              dEN + 2 * r, st));
+            }
+            for (int r : act_hi) {
+                const Sys& y = S[r];
+                NEGF_TRY(energy_launch<double>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.G, y.Sc,
+                                               dEN + 2 * r, st));
+            }
+            return NEGF_OK;
+        }));
+        HIP_TRY(hipMemcpyAsync(hEN.data(), dEN, sizeof(double) * 2 * batch, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const auto t_now = std::chrono::steady_clock::now();
+        const double ms = std::chrono::duration<double, std::milli>(t_now - t_prev).count();
+        t_prev = t_now;
+
+        // stopping rule per system
+        std::vector<int> dy_lo, dy_hi;
+        for (int r = 0; r < batch; ++r) {
+            Sys& y = S[r];
+            if (y.phase == PH_DONE) continue;
+            const double E = hEN[2 * r] + systems[y.b].e_nn, N = hEN[2 * r + 1];
+            y.E = E;
+            y.N = N;
+            const int step = (y.phase == PH_F64 ? y.steps_low : 0) + y.k;
+            if (!std::isfinite(E) || !std::isfinite(N)) {
+                set_error("energy or particle number not finite at step %d (system %d)", step, y.b);
+                rc = NEGF_ENAN;
+                y.phase = PH_DONE;
+                continue;
+            }
+            const double dE = std::isnan(y.E_prev) ? NAN : E - y.E_prev;
+            // a fixed-count run ignores the tolerance; the float64 refinement of
+            // the mixed form has its own
+            const double tol = (low && y.phase == PH_F64 && o->refine_tol > 0) ? o->refine_tol : o->tol;
+            bool stop = false;
+            if (!fixed && y.k >= 1 && std::fabs(dE) < tol) {
+                y.conv = true;
+                stop = true;
+            }
+            if (y.k >= y.limit) stop = true;
+            if (log && log_n && y.log_n < log_cap)
+                log[(size_t)y.b * log_cap + y.log_n++] =
+                    negf_iter_log_t{step, y.phase == PH_LOW ? o->dtype : NEGF_F64, E, dE, N, ms};
+            if (!stop) {
+                y.E_prev = E;
+                ++y.k;
+                (y.phase == PH_LOW ? dy_lo : dy_hi).push_back(r);
+                continue;
+            }
+            if (y.phase == PH_LOW) {
+                y.steps_low = y.k;
+                NEGF_TRY((convert<double, float>(y.Gf, y.G, y.nn * n_tau, st)));
+                if (fixed) {
+                    y.phase = PH_DONE;
+                } else {
+                    y.phase = PH_F64;
+                    y.k = 0;
+                    y.E_prev = NAN;
+                    y.conv = false;
+                    y.limit = o->max_iter > y.steps_low ? o->max_iter - y.steps_low : 1;
+                }
+            } else {
+                y.phase = PH_DONE;
+            }
+        }
+        if (rc != NEGF_OK) break;
+        // (b) Dyson step of every system that goes on
+        if (!dy_lo.empty() || !dy_hi.empty()) {
+            std::string keyD = "D";
+            for (int r : dy_lo) keyD += " l" + std::to_string(r);
+            for (int r : dy_hi) keyD += " h" + std::to_string(r);
+            NEGF_TRY(run_segment(gD, keyD, graphs, gS, st, [&]() -> int {
+                for (int r : dy_lo) {
+                    const Sys& y = S[r];
+                    NEGF_TRY(dyson_run<float>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.eps, y.C, y.mu, y.Sig0,
+                                              y.Gf, y.Scf, o->alpha, o->symmetrize, o->conv_algo, y.Gf, st));
+                }
+                for (int r : dy_hi) {
+                    const Sys& y = S[r];
+                    NEGF_TRY(dyson_run<double>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.eps, y.C, y.mu,
+                                               y.Sig0, y.G, y.Sc, o->alpha, o->symmetrize, o->conv_algo, y.G, st));
+                }
+                return NEGF_OK;
+            }));
+        }
+    }
+    gS.drop();
+    gD.drop();
     HIP_TRY(hipStreamSynchronize(st));
-    if (E_out) *E_out = E;
-    if (N_out) *N_out = N;
-    if (iters) *iters = total;
+    int n_unconv = 0;
+    for (const Sys& y : S) {
+        if (E_out) E_out[y.b] = y.E;
+        if (N_out) N_out[y.b] = y.N;
+        if (iters) iters[y.b] = y.steps_low + y.k;
+        if (log_n) log_n[y.b] = y.log_n;
+        if (!fixed && !y.conv) ++n_unconv;
+    }
     if (rc != NEGF_OK) return rc;
-    if (!fixed && !conv) {
-        set_error("SCF not converged after %d steps", total);
+    if (n_unconv) {
+        set_error("SCF not converged for %d of %d system(s)", n_unconv, batch);
         return NEGF_ENOCONV;
     }
     return NEGF_OK;
+}
+
+extern "C" int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* o, const double* G_guess,
+                        double* G_out, double* E_out, double* N_out, int* iters, negf_iter_log_t* log, int log_cap,
+                        double* hf_E, double* hf_mu, void* stream) {
+    NEGF_REQUIRE(sys, "NULL argument");
+    double* guess = const_cast<double*>(G_guess);
+    int ln = 0;
+    return negf_scf_batched(ctx, 1, sys, o, G_guess ? &guess : nullptr, G_out ? &G_out : nullptr, E_out, N_out,
+                            iters, log, log_cap, log ? &ln : nullptr, hf_E, hf_mu, stream);
 }

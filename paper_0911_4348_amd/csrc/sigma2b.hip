@@ -22,7 +22,10 @@
 // low-precision modes first scale every slice by an exact power of two
 // (2^e_q max|G_q| in [1/2, 1)) and unscale the result, so intermediate products
 // of small slices stay in range; only the stored float32 result can underflow.
+#include <algorithm>
+#include <cmath>
 #include <string>
+#include <vector>
 #include <type_traits>
 
 #include "common.h"
@@ -86,12 +89,10 @@ constexpr int waves_per_eu() {
 // loads of panel p+1 are in flight into registers, then written to the other
 // LDS buffer; one barrier per panel.
 template <int MODE, int IB, int JB, bool DB>
-__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k_sigma2b(int n, int n_tau, int n_iblk,
-                                                     typename Cfg<MODE>::T sigma,
-                                                     const typename Cfg<MODE>::T* __restrict__ V,
-                                                     const typename Cfg<MODE>::T* __restrict__ G,
-                                                     const int* __restrict__ ex,
-                                                     typename Cfg<MODE>::T* __restrict__ Sc) {
+__device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, typename Cfg<MODE>::T sigma,
+                                         const typename Cfg<MODE>::T* __restrict__ V,
+                                         const typename Cfg<MODE>::T* __restrict__ G, const int* __restrict__ ex,
+                                         typename Cfg<MODE>::T* __restrict__ Sc, unsigned char* smem_raw) {
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
     constexpr int NT = IB * 64;
@@ -102,7 +103,6 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
     constexpr int RP = NT / CW;
     constexpr int NSLOT = (BK + RP - 1) / RP;
     static_assert(NT % CW == 0, "threads must cover whole staging rows");
-    extern __shared__ unsigned char smem_raw[];
     constexpr size_t SB = stage_bytes<MODE, JB>();
     unsigned char* stage0 = smem_raw;
     T* Abuf = reinterpret_cast<T*>(smem_raw + (DB ? 2 : 1) * SB);         // [2][16][BK + 1]
@@ -116,8 +116,6 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
     T* Vt = reinterpret_cast<T*>(stage0);                                 // V tile [16][GS_LD] (buffer 0)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const long lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int pair = (int)(lb / n_iblk), iblk = (int)(lb % n_iblk);
     const int q = pair, qb = n_tau - 1 - pair;
     const bool middle = (q == qb);
     const long nn = (long)n * n;
@@ -337,6 +335,86 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
     }
 }
 
+// One workgroup per (slice pair, block of IB rows i), XCD-aware block order.
+template <int MODE, int IB, int JB, bool DB>
+__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k_sigma2b(
+    int n, int n_tau, int n_iblk, typename Cfg<MODE>::T sigma, const typename Cfg<MODE>::T* __restrict__ V,
+    const typename Cfg<MODE>::T* __restrict__ G, const int* __restrict__ ex, typename Cfg<MODE>::T* __restrict__ Sc) {
+    extern __shared__ unsigned char smem_raw[];
+    const long lb = xcd_remap(blockIdx.x, gridDim.x);
+    s2b_tile<MODE, IB, JB, DB>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, ex, Sc, smem_raw);
+}
+
+// One system of a batch for the persistent kernel. Its work items are
+// item0 .. item0 + n_pairs * n_iblk - 1, ordered by slice pair, then row block.
+template <class T>
+struct S2BInst {
+    const T* V;
+    const T* G;
+    T* Sc;
+    const int* ex;
+    long item0;
+    T sigma;
+    int n, n_iblk, n_pairs;
+};
+
+// Item ranges of the 8 per-XCD queues: queue x holds items [c[x], c[x+1]).
+struct XcdCuts {
+    long c[9];
+};
+
+// The persistent form holds a few more live values (the queue state) than the
+// one-item-per-workgroup form; this configuration needs a lower occupancy target
+// to stay free of spills there.
+template <int MODE, int IB, int JB, bool DB>
+constexpr int waves_per_eu_batched() {
+    return (MODE == MODE_BF16 && IB == 8 && JB <= 8 && !DB) ? 3 : waves_per_eu<MODE, IB, JB, DB>();
+}
+
+// Persistent Sigma-2B over a batch of systems of different n_b (same n_tau).
+// The grid is sized to the resident capacity of the chip; each workgroup takes
+// items from the queue of its own XCD (consecutive items share a slice pair
+// and so that XCD's L2), then steals from the other queues until all eight
+// are empty. heads[0..7] count taken items per queue and must be zero at
+// launch. Every workgroup leaves after eight failed probes.
+template <int MODE, int IB, int JB, bool DB>
+__global__ __launch_bounds__(IB * 64, (waves_per_eu_batched<MODE, IB, JB, DB>())) void k_sigma2b_batched(
+    const S2BInst<typename Cfg<MODE>::T>* __restrict__ inst, int n_inst, int n_tau, XcdCuts cuts, int* heads) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ long s_item;
+    const int x = blockIdx.x & 7;       // workgroups are dealt to the XCDs round-robin
+    int probe = 0;
+    while (probe < 8) {
+        if (threadIdx.x == 0) {
+            const int y = (x + probe) & 7;
+            const long it = cuts.c[y] + atomicAdd(&heads[y], 1);
+            s_item = it < cuts.c[y + 1] ? it : -1;
+        }
+        __syncthreads();
+        const long it = s_item;
+        __syncthreads();
+        if (it < 0) {
+            ++probe;
+            continue;
+        }
+        int lo = 0, hi = n_inst - 1;    // last system with item0 <= it
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (inst[mid].item0 <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const long local = it - inst[lo].item0;
+        const int nib = inst[lo].n_iblk;
+        s2b_tile<MODE, IB, JB, DB>(inst[lo].n, n_tau, (int)(local / nib), (int)(local % nib), inst[lo].sigma,
+                                   inst[lo].V, inst[lo].G, inst[lo].ex, inst[lo].Sc, smem_raw);
+    }
+}
+
+__global__ void k_zero_int(int* p, int count) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0;
+}
+
 // ex[q] = e with 2^e max|G_q| in [1/2, 1) (0 for an all-zero slice)
 __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __restrict__ G, int* ex) {
     __shared__ float red[256];
@@ -503,6 +581,213 @@ int sigma2b_tune(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T
         return NEGF_EINVAL;
     }
     ctx->filled[tune_key(mode, n)] = arg;
+    if (best) *best = arg;
+    return NEGF_OK;
+}
+
+// ============================================================== batched (persistent) form
+namespace {
+
+template <int MODE, int IB, int JB, bool DB>
+int launch_batched_cfg(const S2BBatch& pl, hipStream_t st) {
+    typedef typename Cfg<MODE>::T T;
+    const int np = (pl.max_n + 15) & ~15;
+    const size_t smem = lds_bytes<MODE, IB, JB, DB>(np);
+    if (smem + 64 > 160 * 1024) {
+        set_error("n_b = %d too large for this Sigma-2B tile configuration's LDS budget", pl.max_n);
+        return NEGF_EINVAL;
+    }
+    auto kern = k_sigma2b_batched<MODE, IB, JB, DB>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64));
+        attr_set = true;
+    }
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, IB * 64, smem));
+    if (occ < 1) {
+        set_error("Sigma-2B tile configuration does not fit a compute unit at n_b = %d", pl.max_n);
+        return NEGF_EINVAL;
+    }
+    long grid = (long)occ * pl.n_cu;
+    if (grid > pl.n_items) grid = pl.n_items;
+    if (grid < 1) return NEGF_OK;
+    XcdCuts cuts;
+    for (int x = 0; x < 9; ++x) cuts.c[x] = pl.cuts[x];
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pl.heads, 8);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(IB * 64), smem, st,
+                       (const S2BInst<T>*)pl.d_inst, pl.n_inst, pl.n_tau, cuts, pl.heads);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+template <int MODE>
+int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
+    switch (cfg) {
+        case 0: return launch_batched_cfg<MODE, 8, 13, false>(pl, st);
+        case 1: return launch_batched_cfg<MODE, 8, 7, false>(pl, st);
+        case 2: return launch_batched_cfg<MODE, 4, 13, false>(pl, st);
+        case 3: return launch_batched_cfg<MODE, 4, 7, false>(pl, st);
+        case 4: return launch_batched_cfg<MODE, 8, 7, true>(pl, st);
+        default: return launch_batched_cfg<MODE, 4, 13, true>(pl, st);
+    }
+}
+
+int cfg_rows(int cfg) { return (cfg == 0 || cfg == 1 || cfg == 4) ? 8 : 4; }
+
+std::string batch_key(int mode, const std::vector<int>& n) {
+    std::string k = "s2bB_" + std::to_string(mode);
+    for (int v : n) k += "_" + std::to_string(v);
+    return k;
+}
+
+template <class T>
+int prepare_typed(negf_ctx* ctx, const std::string& tag, int batch, const int* n, int n_tau, const int* sigma,
+                  const void* const* V, const void* const* G, void* const* Sc, int pair_lim, S2BBatch* pl,
+                  hipStream_t st) {
+    // systems in order of decreasing n_b: the largest items are taken first
+    std::vector<int> order(batch);
+    for (int b = 0; b < batch; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    const int rows = cfg_rows(pl->cfg);
+    const int n_pairs_all = (n_tau + 1) / 2;
+    const int n_pairs = pair_lim > 0 && pair_lim < n_pairs_all ? pair_lim : n_pairs_all;
+    std::vector<S2BInst<T>> hi(batch);
+    std::vector<double> cost(batch);
+    int* ex = nullptr;
+    if (pl->mode != MODE_F64) NEGF_TRY(scratch_t(ctx, ("s2bB_ex_" + tag).c_str(), (size_t)batch * n_tau, &ex));
+    long items = 0;
+    double total = 0.0;
+    pl->n_sorted.assign(batch, 0);
+    pl->G_sorted.assign(batch, nullptr);
+    pl->ex_sorted.assign(batch, nullptr);
+    pl->max_n = 0;
+    for (int r = 0; r < batch; ++r) {
+        const int b = order[r];
+        S2BInst<T>& I = hi[r];
+        I.V = (const T*)V[b];
+        I.G = (const T*)G[b];
+        I.Sc = (T*)Sc[b];
+        I.ex = ex ? ex + (long)r * n_tau : nullptr;
+        I.item0 = items;
+        I.sigma = (T)sigma[b];
+        I.n = n[b];
+        I.n_iblk = (n[b] + rows - 1) / rows;
+        I.n_pairs = n_pairs;
+        items += (long)n_pairs * I.n_iblk;
+        cost[r] = (double)n[b] * n[b] * n[b];
+        total += cost[r] * n_pairs * I.n_iblk;
+        pl->n_sorted[r] = n[b];
+        pl->G_sorted[r] = G[b];
+        pl->ex_sorted[r] = ex ? ex + (long)r * n_tau : nullptr;
+        if (n[b] > pl->max_n) pl->max_n = n[b];
+    }
+    // equal-cost contiguous item ranges, one per XCD
+    pl->cuts.assign(9, items);
+    pl->cuts[0] = 0;
+    double acc = 0.0;
+    int x = 1;
+    for (int r = 0; r < batch && x < 8; ++r) {
+        const long cnt = (long)n_pairs * hi[r].n_iblk;
+        const double seg = cost[r] * cnt;
+        while (x < 8 && acc + seg >= total * x / 8.0) {
+            long off = (long)std::ceil((total * x / 8.0 - acc) / cost[r]);
+            if (off > cnt) off = cnt;
+            if (off < 0) off = 0;
+            pl->cuts[x] = hi[r].item0 + off;
+            ++x;
+        }
+        acc += seg;
+    }
+    for (int y = 1; y < 9; ++y)
+        if (pl->cuts[y] < pl->cuts[y - 1]) pl->cuts[y] = pl->cuts[y - 1];
+    pl->n_inst = batch;
+    pl->n_tau = n_tau;
+    pl->n_items = items;
+    NEGF_TRY(upload(ctx, ("s2bB_inst_" + tag).c_str(), hi.data(), sizeof(S2BInst<T>) * batch, st, &pl->d_inst));
+    NEGF_TRY(scratch_t(ctx, ("s2bB_heads_" + tag).c_str(), 8, &pl->heads));
+    return NEGF_OK;
+}
+
+}  // namespace
+
+int s2b_batch_prepare(negf_ctx* ctx, const char* tag, int dtype, int batch, const int* n, int n_tau,
+                      const int* sigma, const void* const* V, const void* const* G, void* const* Sc, int pair_lim,
+                      S2BBatch* pl, hipStream_t st) {
+    pl->mode = dtype == NEGF_F64 ? MODE_F64 : (dtype == NEGF_BF16 ? MODE_BF16 : MODE_F32);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&pl->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<int> ns(n, n + batch);
+    std::sort(ns.begin(), ns.end());
+    pl->key = batch_key(pl->mode, ns);
+    if (pl->cfg < 0) {
+        auto it = ctx->filled.find(pl->key);
+        pl->cfg = it != ctx->filled.end() ? it->second : default_cfg(pl->mode, 0);
+    }
+    const std::string t(tag);
+    if (pl->mode == MODE_F64)
+        return prepare_typed<double>(ctx, t, batch, n, n_tau, sigma, V, G, Sc, pair_lim, pl, st);
+    return prepare_typed<float>(ctx, t, batch, n, n_tau, sigma, V, G, Sc, pair_lim, pl, st);
+}
+
+// Stream-ordered and free of host synchronisation: may be captured in a graph.
+int s2b_batch_launch(const S2BBatch& pl, hipStream_t st) {
+    if (pl.mode != MODE_F64) {
+        for (int r = 0; r < pl.n_inst; ++r) {
+            hipLaunchKernelGGL(k_slice_exponent, dim3(pl.n_tau), dim3(256), 0, st, pl.n_sorted[r],
+                               (const float*)pl.G_sorted[r], pl.ex_sorted[r]);
+            LAUNCH_CHECK();
+        }
+    }
+    if (pl.mode == MODE_F64) return launch_batched<MODE_F64>(pl, pl.cfg, st);
+    if (pl.mode == MODE_BF16) return launch_batched<MODE_BF16>(pl, pl.cfg, st);
+    return launch_batched<MODE_F32>(pl, pl.cfg, st);
+}
+
+// Tile autotuner for a batch: every configuration is timed on the first
+// pair_lim slice pairs of every system (the same mix of n_b as the full run),
+// and the fastest is stored for this multiset of n_b.
+int s2b_batch_tune(negf_ctx* ctx, int dtype, int batch, const int* n, int n_tau, const int* sigma,
+                   const void* const* V, const void* const* G, void* const* Sc, int pair_lim, int* best, double* ms,
+                   hipStream_t st) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int arg = -1;
+    float tbest = 0.f;
+    std::string key;
+    for (int c = 0; c < kNumCfg; ++c) {
+        S2BBatch pl;
+        pl.cfg = c;
+        NEGF_TRY(s2b_batch_prepare(ctx, "tune", dtype, batch, n, n_tau, sigma, V, G, Sc, pair_lim, &pl, st));
+        key = pl.key;
+        int rc = s2b_batch_launch(pl, st);
+        if (rc == NEGF_EINVAL) {
+            if (ms) ms[c] = -1.0;
+            continue;
+        }
+        NEGF_TRY(rc);
+        HIP_TRY(hipEventRecord(e0, st));
+        NEGF_TRY(s2b_batch_launch(pl, st));
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (ms) ms[c] = t;
+        if (arg < 0 || t < tbest) {
+            arg = c;
+            tbest = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (arg < 0) {
+        set_error("no Sigma-2B tile configuration fits this batch");
+        return NEGF_EINVAL;
+    }
+    ctx->filled[key] = arg;
     if (best) *best = arg;
     return NEGF_OK;
 }

@@ -1,0 +1,166 @@
+"""GPU parity of the batched forms: the persistent Sigma-2B launch over systems
+of different n_b and the batched self-consistent loop (graph-replayed
+iterations), each system against the float64 oracle and against the
+single-system entry points."""
+import numpy as np
+import pytest
+
+import paper_0911_4348_amd as negf
+import workloads as W
+from oracle import sigma as S, scf as SC
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_mod):
+    c = negf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+SIZES = [37, 5, 100, 1, 64, 19, 64, 213]
+
+
+def _batch(n_tau, sizes=SIZES):
+    Vs = [np.abs(W.random_symmetric(n, 500 + k)) + 0.1 for k, n in enumerate(sizes)]
+    Gs = [W.random_symmetric_slices(n, n_tau, 600 + k) for k, n in enumerate(sizes)]
+    return Vs, Gs
+
+
+@pytest.mark.parametrize("sizes,n_tau", [(SIZES, 9), (SIZES, 4), ([100, 64, 37, 64], 129)])
+def test_sigma2b_batched_f64(ctx, torch_mod, sizes, n_tau):
+    """Against the oracle; the last case has several times more work items than
+    resident workgroups, so every workgroup loops over the queues and steals."""
+    print(f"sigma2b batched f64 n_tau={n_tau} sizes={sizes}", flush=True)
+    Vs, Gs = _batch(n_tau, sizes)
+    outs = negf.sigma2b_batched(ctx, [dev(torch_mod, v) for v in Vs], [dev(torch_mod, g) for g in Gs], 2)
+    torch_mod.cuda.synchronize()
+    for V, G, o in zip(Vs, Gs, outs):
+        assert relerr(host(o), S.sigma2b(V, G, 2)) < TOL64, G.shape
+
+
+@pytest.mark.parametrize("cfg", range(6))
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_sigma2b_batched_every_config_matches_single(ctx, torch_mod, cfg, dtype):
+    """With the same tile configuration the persistent launch does the same
+    arithmetic per element as the one-launch-per-system kernel: bitwise equal."""
+    print(f"sigma2b batched cfg={cfg} {dtype}", flush=True)
+    sizes = [37, 221, 5, 64]
+    Vs, Gs = _batch(5, sizes)
+    wt = torch_mod.float64 if dtype == "f64" else torch_mod.float32
+    Vd = [dev(torch_mod, v, wt) for v in Vs]
+    Gd = [dev(torch_mod, g, wt) for g in Gs]
+    for n in sizes:
+        negf.sigma2b_set_config(ctx, n, dtype, cfg)
+    negf.sigma2b_batched_set_config(ctx, sizes, dtype, cfg)
+    singles = [host(negf.sigma2b(ctx, v, g, 2, dtype=dtype)) for v, g in zip(Vd, Gd)]
+    outs = negf.sigma2b_batched(ctx, Vd, Gd, 2, dtype=dtype)
+    for o, s1 in zip(outs, singles):
+        assert np.array_equal(host(o), s1)
+
+
+def test_sigma2b_batched_tuner(ctx, torch_mod):
+    sizes = [37, 100, 64]
+    Vs, Gs = _batch(33, sizes)
+    Vd = [dev(torch_mod, v) for v in Vs]
+    Gd = [dev(torch_mod, g) for g in Gs]
+    best, ms = negf.sigma2b_batched_tune(ctx, Vd, Gd, 2, pair_lim=4)
+    assert 0 <= best < 6 and ms[best] > 0 and all(m == -1.0 or m > 0 for m in ms)
+    outs = negf.sigma2b_batched(ctx, Vd, Gd, 2)
+    for V, G, o in zip(Vs, Gs, outs):
+        assert relerr(host(o), S.sigma2b(V, G, 2)) < TOL64
+
+
+def test_sigma2b_batched_rejects_bad_args(ctx, torch_mod):
+    g = torch_mod.zeros((3, 4, 4), dtype=torch_mod.float64, device="cuda")
+    v = torch_mod.zeros((4, 4), dtype=torch_mod.float64, device="cuda")
+    with pytest.raises(negf.NegfError):
+        negf.sigma2b_batched(ctx, [v, v], [g, g], 2, outs=[g, g])     # Sigma_c aliases G
+    with pytest.raises(negf.NegfError):
+        negf.sigma2b_batched(ctx, [v], [g], 3)                         # sigma
+
+
+def _scan_small(k_list, M=32):
+    """H3+ scan members on small grids: uneven n_b, one tau grid."""
+    out = []
+    for k in k_list:
+        R = W.scan_R(k, 8)
+        n_e = 4 + k // 2
+        out.append(W.h3p_1d(R=R, half_width=6.0 + R, n_e=n_e, n_g=4, beta=20.0, tau_kind="uniform", M=M))
+    return out
+
+
+def test_scf_batched_matches_oracle_per_instance(ctx):
+    systems = _scan_small([0, 3, 7, 5])
+    print("scf batched sizes", [s.n_b for s in systems], flush=True)
+    outs = negf.scf_batched(ctx, systems, alpha=0.3, tol=1e-8, tune=True)
+    for s, o in zip(systems, outs):
+        ref = SC.scf(s, tol=1e-8)
+        print(f"  n_b={s.n_b} R={s.centres[2]:.3f}: E={o.E:.12f} iters={o.iters} oracle {ref.E:.12f} {ref.iters}")
+        assert o.iters == ref.iters
+        assert abs(o.E - ref.E) < TOL64 * abs(ref.E)
+        assert abs(o.hf_E - s.e_nn - ref.hf.E) < TOL64 * abs(ref.hf.E)   # hf_E includes e_nn
+        assert relerr(host(o.G), ref.G) < 1e-9
+
+
+def test_scf_batched_graph_replay_equals_direct(ctx):
+    """Every iteration replayed from recorded graphs gives the same iterates as
+    launching each iteration directly (fixed count, so both run the same steps)."""
+    systems = _scan_small([1, 6, 2])
+    a = negf.scf_batched(ctx, systems, fixed_iters=6, graphs=True)
+    b = negf.scf_batched(ctx, systems, fixed_iters=6, graphs=False)
+    for x, y in zip(a, b):
+        assert x.iters == y.iters == 6
+        assert x.E == y.E
+        assert np.array_equal(host(x.G), host(y.G))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_scf_batched_mixed_precision(ctx, dtype):
+    systems = _scan_small([0, 4, 7])
+    outs = negf.scf_batched(ctx, systems, alpha=0.3, tol=1e-6, dtype=dtype, refine_tol=1e-9)
+    for s, o in zip(systems, outs):
+        ref = SC.scf(s, tol=1e-10)
+        print(f"  mixed {dtype} n_b={s.n_b}: |E-E_oracle| = {abs(o.E - ref.E):.2e} Ha, iters {o.iters}")
+        assert abs(o.E - ref.E) < 1e-6
+        single = negf.scf(ctx, s, alpha=0.3, tol=1e-6, dtype=dtype, refine_tol=1e-9)
+        assert abs(single.E - o.E) < 1e-8
+
+
+def test_scf_batched_per_system_stopping(ctx):
+    """Systems that converge early stay frozen: each result equals the
+    single-system run with the same options."""
+    systems = _scan_small([7, 0])
+    outs = negf.scf_batched(ctx, systems, alpha=0.5, tol=1e-7)
+    for s, o in zip(systems, outs):
+        one = negf.scf(ctx, s, alpha=0.5, tol=1e-7)
+        assert one.iters == o.iters
+        assert abs(one.E - o.E) < 1e-12 * abs(o.E)
+        assert relerr(host(o.G), host(one.G)) < 1e-11
