@@ -94,6 +94,78 @@ def cpu_baseline(V, G, sigma, target_s=15.0):
                       f"{dt:.1f} s); flops counted as the GPU's algorithmic count per slice"}
 
 
+def scf_compare(torch, negf, W, seed=100000):
+    """Wall time to |E_k - E_(k-1)| < 1e-6 Ha for one held-out random potential on the n_b = 199 grid
+    (1025 tau points, beta = 50): plain float64 from the HF start, the mixed forms, and the learned
+    start; each final energy against a float64 reference converged to 1e-10 Ha."""
+    from paper_0911_4348_amd import learned_guess as LG
+    s = W.random_potential_system(seed)
+    ctx = negf.Context(0)
+    kw = dict(conv=negf.CONV_FFT, want_G=False, max_iter=400)
+    ref = negf.scf(ctx, s, tol=1e-10, **kw)
+    negf.scf(ctx, s, fixed_iters=1, dtype="bf16", **kw)         # kernel loading for the mixed forms
+    runs = {"plain_f64": dict(tol=1e-6), "mixed_f32": dict(tol=1e-6, dtype="f32", refine_tol=1e-6),
+            "mixed_bf16": dict(tol=1e-6, dtype="bf16", refine_tol=1e-6)}
+    params = None
+    if os.path.exists(LG.WEIGHTS):
+        p, scale, _ = LG.load()
+        params = torch.from_numpy(p).cuda()
+        runs["learned_f64"] = dict(tol=1e-6, guess=params, guess_scale=scale)
+        runs["learned_bf16"] = dict(tol=1e-6, dtype="bf16", refine_tol=1e-6, guess=params, guess_scale=scale)
+    res = {}
+    for name, o in runs.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = negf.scf(ctx, s, **kw, **o)
+        torch.cuda.synchronize()
+        res[name] = {"s": round(time.perf_counter() - t0, 3), "steps": r.iters,
+                     "abs_err_Ha": float(abs(r.E - ref.E))}
+    base = res["plain_f64"]["s"]
+    for v in res.values():
+        v["speedup_vs_plain_f64"] = round(base / v["s"], 3)
+    ctx.close()
+    return {"workload": f"random soft-Coulomb potential seed {seed} (held out), n_b = 199, 1025 tau points, "
+                        f"beta = 50, alpha = 0.3, stop at |dE| < 1e-6 Ha, HF included",
+            "E_ref": ref.E, "runs": res}
+
+
+def run_scan(args, torch, negf, W):
+    """Bond-length scan of linear H3+ (R = 1 + 2k/(n-1), uneven n_b = 149..399, 1025 tau points,
+    beta = 100), every instance from its HF start to |E_k - E_(k-1)| < 1e-6 Ha: either all at once
+    through negf_scf_batched (persistent Sigma-2B launches, recorded iterations, tuned tiles) or one
+    after another through negf_scf (the plain path). Prints one JSON line with the wall time."""
+    systems = W.config_scan(args.scan_n)
+    ctx = negf.Context(0)
+    # kernel loading and table set-up outside the timed region: one step of the smallest instance
+    negf.scf(ctx, systems[0], fixed_iters=1, dtype=args.dtype, conv=negf.CONV_FFT, want_G=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kw = dict(tol=1e-6, dtype=args.dtype, refine_tol=1e-6, conv=negf.CONV_FFT, want_G=False, max_iter=400,
+              allow_noconv=True, tune=True)
+    if args.scan_mode == "batched":
+        outs = negf.scf_batched(ctx, systems, **kw)
+    else:
+        outs = [negf.scf_batched(ctx, [s], **kw)[0] for s in systems]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flops = sum(sigma2b_flops(s.n_b, s.n_tau) * (o.iters + 1) for s, o in zip(systems, outs))
+    out = {
+        "metric": "SCF wall time to 1e-6 Ha, 64-instance H3+ bond-length scan",
+        "value": round(wall, 2), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"linear H3+ scan, {len(systems)} instances, R = 1..3, n_b = "
+                               f"{min(s.n_b for s in systems)}..{max(s.n_b for s in systems)}, 1025 tau points, "
+                               f"beta = 100, alpha = 0.3, HF start, |dE| < 1e-6 Ha",
+                   "mode": args.scan_mode},
+        "sigma2b_tflops_avg": round(flops / wall / 1e12, 2),
+        "instances": [{"R": round(float(s.centres[2]), 6), "n_b": s.n_b, "E": o.E, "E_hf": o.hf_E,
+                       "iters": o.iters, "status": o.status} for s, o in zip(systems, outs)],
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,7 +173,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-scf", action="store_true", help="skip the SCF time-to-accuracy comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="sigma", choices=["sigma", "scan"],
+                    help="sigma: the Sigma-2B microbenchmark step (default); scan: the 64-instance H3+ "
+                         "bond-length scan solved to 1e-6 Ha")
+    ap.add_argument("--scan-mode", default="batched", choices=["batched", "sequential"])
+    ap.add_argument("--scan-n", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed region, run one elementwise float64 copy of BYTES "
                          "(reads BYTES, writes BYTES) to calibrate HBM byte counters")
@@ -116,6 +194,8 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "scan":
+        return run_scan(args, torch, negf, W)
     dev = torch.device("cuda:0")
     s = W.config_sigma_bench()
     n, M = s.n_b, s.M
@@ -206,10 +286,15 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nel * 8
         del src, dst
+    if not args.no_scf:
+        ctx.close()
+        ctx = None
+        out["scf_time_to_1e-6"] = scf_compare(torch, negf, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(V, Gh, s.sigma, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    ctx.close()
+    if ctx is not None:
+        ctx.close()
 
 
 if __name__ == "__main__":

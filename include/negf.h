@@ -326,15 +326,18 @@ int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* opts,
  * rounding: the tile configuration may differ).
  * systems (host, batch). G_guess, G_out (host arrays of batch device pointers,
  * each float64 [n_tau][n_b][n_b]; the arrays and their entries nullable).
- * E_out, N_out, iters, hf_E, hf_mu, log_n (host, batch entries, nullable).
+ * E_out, N_out, iters, hf_E, hf_mu, log_n (host, batch entries, nullable);
+ * status (host, batch ints, nullable): NEGF_OK, NEGF_ENOCONV, or NEGF_ENAN for a
+ * system whose energy became non-finite (it stops there; the others go on).
  * log (host, nullable): batch x log_cap records, system b from b*log_cap; the
  * record's ms is the wall time of the whole batch iteration.
- * Errors: as negf_scf; NEGF_ENOCONV if any system did not converge. Runs on a
+ * Errors: as negf_scf; NEGF_ENAN if any system failed so, else NEGF_ENOCONV if
+ * any did not converge (all outputs valid in both cases). Runs on a
  * stream of its own that first waits for `stream`; returns after it finished. */
 int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* systems,
                      const negf_opts_t* opts, double* const* G_guess, double* const* G_out,
-                     double* E_out, double* N_out, int* iters, negf_iter_log_t* log, int log_cap,
-                     int* log_n, double* hf_E, double* hf_mu, void* stream);
+                     double* E_out, double* N_out, int* iters, int* status, negf_iter_log_t* log,
+                     int log_cap, int* log_n, double* hf_E, double* hf_mu, void* stream);
 
 /* ------------------------------------------------------------------ learned initial guess */
 /* A tau-resolved float32 MLP predicts dG_ij(tau) = G(tau) - G0(tau) of the converged

@@ -100,7 +100,7 @@ _SIGS = {
     "negf_scf": (C.c_int, [_VP, C.POINTER(SystemT), C.POINTER(OptsT), _VP, _VP, _DP, _DP, _IP,
                            C.POINTER(IterLogT), C.c_int, _DP, _DP, _VP]),
     "negf_scf_batched": (C.c_int, [_VP, C.c_int, C.POINTER(SystemT), C.POINTER(OptsT), _VP, _VP, _DP, _DP, _IP,
-                                   C.POINTER(IterLogT), C.c_int, _IP, _DP, _DP, _VP]),
+                                   _IP, C.POINTER(IterLogT), C.c_int, _IP, _DP, _DP, _VP]),
     "negf_sigma2b_batched": (C.c_int, [_VP, C.c_int, _IP, C.c_int, _IP, _VP, _VP, _VP, C.c_int, _VP]),
     "negf_sigma2b_batched_set_config": (C.c_int, [_VP, C.c_int, _IP, C.c_int, C.c_int]),
     "negf_sigma2b_batched_tune": (C.c_int, [_VP, C.c_int, _IP, C.c_int, _IP, _VP, _VP, _VP, C.c_int, C.c_int,
@@ -292,7 +292,8 @@ def hf(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1000, str
     return HFState(eps, Cm, rho, S0, mu.value, E.value, it.value)
 
 
-def hf_batched(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1000, stream=None):
+def hf_batched(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1000, allow_noconv=False,
+               stream=None):
     """negf_hf_batched on stacked device tensors T[B,n,n], v[B,n], V[B,n,n] (float64).
     Returns (eps[B,n], C[B,n,n], rho[B,n,n], Sigma0[B,n,n], mu[B], E_hf[B], iters[B]); the last
     three are numpy arrays."""
@@ -306,10 +307,12 @@ def hf_batched(ctx: Context, T, v, V, n_elec, sigma, beta, tol=1e-13, max_iter=1
     mu = np.zeros(B)
     E = np.zeros(B)
     it = np.zeros(B, dtype=np.int32)
-    _check(lib().negf_hf_batched(ctx.handle, B, n, _dev_ptr(T), _dev_ptr(v), _dev_ptr(V), float(n_elec),
+    rc = (lib().negf_hf_batched(ctx.handle, B, n, _dev_ptr(T), _dev_ptr(v), _dev_ptr(V), float(n_elec),
                                  int(sigma), float(beta), float(tol), int(max_iter), _dev_ptr(eps), _dev_ptr(Cm),
                                  _dev_ptr(rho), _dev_ptr(S0), _dptr(mu), _dptr(E),
                                  it.ctypes.data_as(_IP), _stream(stream)))
+    if rc != OK and not (allow_noconv and rc == ENOCONV):
+        _check(rc)
     return eps, Cm, rho, S0, mu, E, it
 
 
@@ -442,6 +445,7 @@ def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed
         guess_p = (C.c_void_p * B)(*[_dev_ptr(g) for g in G_guess])
     E, N, hE, hmu = np.zeros(B), np.zeros(B), np.zeros(B), np.zeros(B)
     it, ln = np.zeros(B, dtype=np.int32), np.zeros(B, dtype=np.int32)
+    stat = np.zeros(B, dtype=np.int32)
     cap = (fixed_iters if fixed_iters else max_iter) + max_iter + 4
     logs = (IterLogT * (B * cap))()
     if single:
@@ -451,12 +455,14 @@ def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed
         ln[0] = sum(1 for k in range(cap) if logs[k].ms > 0)
     else:
         rc = lib().negf_scf_batched(ctx.handle, B, structs, C.byref(o), guess_p, Gp, _dptr(E), _dptr(N),
-                                    it.ctypes.data_as(_IP), logs, cap, ln.ctypes.data_as(_IP), _dptr(hE),
-                                    _dptr(hmu), _stream(stream))
-    if rc != OK and not (allow_noconv and rc == ENOCONV):
+                                    it.ctypes.data_as(_IP), stat.ctypes.data_as(_IP), logs, cap,
+                                    ln.ctypes.data_as(_IP), _dptr(hE), _dptr(hmu), _stream(stream))
+    if single:
+        stat[0] = rc
+    if rc != OK and not (allow_noconv and rc in (ENOCONV, ENAN)):
         _check(rc)
     return [SCFOut(Gs[b], float(E[b]), float(N[b]), int(it[b]), float(hE[b]), float(hmu[b]),
-                   _records(logs, b * cap, int(ln[b])), rc) for b in range(B)]
+                   _records(logs, b * cap, int(ln[b])), int(stat[b])) for b in range(B)]
 
 
 def sigma2b_batched(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, stream=None):

@@ -82,7 +82,8 @@ int s2b_batch_tune(negf_ctx* ctx, int dtype, int batch, const int* n, int n_tau,
                    hipStream_t st);
 int hf_run_batched(negf_ctx* ctx, int B, int n_b, const double* T, const double* v, const double* V,
                    double n_elec, int sigma, double beta, double tol, int max_iter, double* eps, double* C,
-                   double* rho, double* Sigma0, double* mu, double* E_hf, int* iters, hipStream_t st);
+                   double* rho, double* Sigma0, double* mu, double* E_hf, int* iters, hipStream_t st,
+                   int* converged = nullptr);
 int hf_run(negf_ctx* ctx, int n_b, const double* T, const double* v, const double* V,
            double n_elec, int sigma, double beta, double tol, int max_iter,
            double* eps, double* C, double* rho, double* Sigma0, double* mu, double* E_hf,

@@ -310,7 +310,8 @@ int transpose_batched(const double* in, double* out, int n, int B, hipStream_t s
 // iterated in lockstep; a system stops changing once its own test passes.
 int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v, const double* V, double n_elec,
                    int sigma, double beta, double tol, int max_iter, double* eps, double* C, double* rho,
-                   double* Sigma0, double* mu_out, double* E_out, int* iters_out, hipStream_t st) {
+                   double* Sigma0, double* mu_out, double* E_out, int* iters_out, hipStream_t st,
+                   int* converged) {
     const long nn = (long)n * n;
     double *A, *Vt, *F, *Cp, *tmp, *f, *rho_old, *dmu, *dres;
     int* dact;
@@ -401,6 +402,7 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
         if (mu_out) mu_out[b] = hmu[b];
         if (E_out) E_out[b] = E[b];
         if (iters_out) iters_out[b] = its[b];
+        if (converged) converged[b] = act[b] ? 0 : 1;
     }
     if (n_active > 0) {
         set_error("HF not converged after %d iterations for %d system(s) (|dE| tol %g)", max_iter, n_active, tol);

@@ -53,6 +53,8 @@ struct Sys {
     int steps_low = 0;
     double E_prev = NAN, E = 0, N = 0;
     bool conv = false;
+    bool nan = false;
+    bool hf_ok = true;       // HF converged; otherwise the system is not iterated
     int log_n = 0;
 };
 
@@ -118,8 +120,8 @@ int validate(const negf_system_t* s, int* n, int* n_tau) {
 
 extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* systems, const negf_opts_t* o,
                                 double* const* G_guess, double* const* G_out, double* E_out, double* N_out,
-                                int* iters, negf_iter_log_t* log, int log_cap, int* log_n, double* hf_E,
-                                double* hf_mu, void* stream) {
+                                int* iters, int* status, negf_iter_log_t* log, int log_cap, int* log_n,
+                                double* hf_E, double* hf_mu, void* stream) {
     NEGF_REQUIRE(ctx && systems && o, "NULL argument");
     NEGF_REQUIRE(batch >= 1 && batch <= 4096, "batch = %d out of range [1, 4096]", batch);
     NEGF_REQUIRE(o->alpha > 0 && o->alpha <= 1, "alpha must be in (0, 1]");
@@ -250,15 +252,17 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             ++r1;
         const int B = r1 - r0;
         std::vector<double> mu(B), E(B);
-        std::vector<int> it(B);
+        std::vector<int> it(B), ok(B, 1);
         const negf_system_t& sg = systems[S[r0].b];
-        NEGF_TRY(hf_run_batched(ctx, B, S[r0].n, S[r0].T, S[r0].v, S[r0].V, sg.n_elec, sg.sigma, sg.beta, hf_tol,
-                                hf_max, S[r0].eps, S[r0].C, S[r0].rho, S[r0].Sig0, mu.data(), E.data(), it.data(),
-                                st));
+        const int hrc = hf_run_batched(ctx, B, S[r0].n, S[r0].T, S[r0].v, S[r0].V, sg.n_elec, sg.sigma, sg.beta,
+                                       hf_tol, hf_max, S[r0].eps, S[r0].C, S[r0].rho, S[r0].Sig0, mu.data(),
+                                       E.data(), it.data(), st, ok.data());
+        if (hrc != NEGF_ENOCONV) NEGF_TRY(hrc);
         for (int r = r0; r < r1; ++r) {
             S[r].mu = mu[r - r0];
             S[r].Ehf = E[r - r0];
             S[r].hf_it = it[r - r0];
+            S[r].hf_ok = ok[r - r0] != 0;
             if (hf_E) hf_E[S[r].b] = S[r].Ehf + systems[S[r].b].e_nn;
             if (hf_mu) hf_mu[S[r].b] = S[r].mu;
         }
@@ -284,10 +288,13 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
 
     // ---------------- iteration
     const bool fixed = o->fixed_iters > 0;
+    int n_hf_fail = 0;
     for (Sys& y : S) {
-        y.phase = low ? PH_LOW : PH_F64;
+        y.phase = !y.hf_ok ? PH_DONE : (low ? PH_LOW : PH_F64);
         y.limit = fixed ? o->fixed_iters : o->max_iter;
+        n_hf_fail += !y.hf_ok;
     }
+    if (n_hf_fail) set_error("HF not converged for %d system(s); those were not iterated", n_hf_fail);
     if (o->tune) {
         // tile autotuner for each arithmetic mode over the whole batch (first 16 slice pairs)
         for (int pass = 0; pass < (low ? 2 : 1); ++pass) {
@@ -392,8 +399,10 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             y.N = N;
             const int step = (y.phase == PH_F64 ? y.steps_low : 0) + y.k;
             if (!std::isfinite(E) || !std::isfinite(N)) {
+                // this system stops; the others go on
                 set_error("energy or particle number not finite at step %d (system %d)", step, y.b);
                 rc = NEGF_ENAN;
+                y.nan = true;
                 y.phase = PH_DONE;
                 continue;
             }
@@ -432,7 +441,6 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
                 y.phase = PH_DONE;
             }
         }
-        if (rc != NEGF_OK) break;
         // (b) Dyson step of every system that goes on
         if (!dy_lo.empty() || !dy_hi.empty()) {
             std::string keyD = "D";
@@ -462,11 +470,15 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
         if (N_out) N_out[y.b] = y.N;
         if (iters) iters[y.b] = y.steps_low + y.k;
         if (log_n) log_n[y.b] = y.log_n;
-        if (!fixed && !y.conv) ++n_unconv;
+        if (status)
+            status[y.b] = y.nan ? NEGF_ENAN : ((!y.hf_ok || (!fixed && !y.conv)) ? NEGF_ENOCONV : NEGF_OK);
+        if ((!fixed && !y.conv && !y.nan) || !y.hf_ok) ++n_unconv;
     }
     if (rc != NEGF_OK) return rc;
     if (n_unconv) {
-        set_error("SCF not converged for %d of %d system(s)", n_unconv, batch);
+        if (n_hf_fail) set_error("HF not converged for %d and SCF for %d of %d system(s)", n_hf_fail,
+                                 n_unconv - n_hf_fail, batch);
+        else set_error("SCF not converged for %d of %d system(s)", n_unconv, batch);
         return NEGF_ENOCONV;
     }
     return NEGF_OK;
@@ -479,5 +491,5 @@ extern "C" int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts
     double* guess = const_cast<double*>(G_guess);
     int ln = 0;
     return negf_scf_batched(ctx, 1, sys, o, G_guess ? &guess : nullptr, G_out ? &G_out : nullptr, E_out, N_out,
-                            iters, log, log_cap, log ? &ln : nullptr, hf_E, hf_mu, stream);
+                            iters, nullptr, log, log_cap, log ? &ln : nullptr, hf_E, hf_mu, stream);
 }

@@ -115,7 +115,11 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
     T* Gbi = XPs + IB * np;                                               // [IB][npj] row i of Gb (scaled)
     T* Vt = reinterpret_cast<T*>(stage0);                                 // V tile [16][GS_LD] (buffer 0)
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // opaque copy of the thread index: in the persistent kernel this keeps the
+    // index arithmetic inside the item loop instead of holding it in registers
+    int tid_ = threadIdx.x;
+    asm volatile("" : "+v"(tid_));
+    const int tid = tid_, lane = tid & 63, w = tid >> 6;
     const int q = pair, qb = n_tau - 1 - pair;
     const bool middle = (q == qb);
     const long nn = (long)n * n;
@@ -363,14 +367,6 @@ struct XcdCuts {
     long c[9];
 };
 
-// The persistent form holds a few more live values (the queue state) than the
-// one-item-per-workgroup form; this configuration needs a lower occupancy target
-// to stay free of spills there.
-template <int MODE, int IB, int JB, bool DB>
-constexpr int waves_per_eu_batched() {
-    return (MODE == MODE_BF16 && IB == 8 && JB <= 8 && !DB) ? 3 : waves_per_eu<MODE, IB, JB, DB>();
-}
-
 // Persistent Sigma-2B over a batch of systems of different n_b (same n_tau).
 // The grid is sized to the resident capacity of the chip; each workgroup takes
 // items from the queue of its own XCD (consecutive items share a slice pair
@@ -378,7 +374,7 @@ constexpr int waves_per_eu_batched() {
 // are empty. heads[0..7] count taken items per queue and must be zero at
 // launch. Every workgroup leaves after eight failed probes.
 template <int MODE, int IB, int JB, bool DB>
-__global__ __launch_bounds__(IB * 64, (waves_per_eu_batched<MODE, IB, JB, DB>())) void k_sigma2b_batched(
+__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k_sigma2b_batched(
     const S2BInst<typename Cfg<MODE>::T>* __restrict__ inst, int n_inst, int n_tau, XcdCuts cuts, int* heads) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ long s_item;

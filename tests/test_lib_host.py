@@ -99,3 +99,33 @@ def test_no_device_reports_enodev(L):
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert L.negf_ctx_create(0, C.byref(h)) == negf.ENODEV
+
+
+def test_batched_entry_points_reject_bad_arguments(L):
+    """Host-side validation of the batched calls (no device is touched)."""
+    n = (C.c_int * 2)(10, 0)
+    sg = (C.c_int * 2)(2, 2)
+    ptrs = (C.c_void_p * 2)(8, 16)
+    outs = (C.c_void_p * 2)(24, 32)
+    rc = L.negf_sigma2b_batched(C.c_void_p(1), 2, n, 5, sg, ptrs, ptrs, outs, 0, None)
+    assert rc == negf.EINVAL and b"n_b[1]" in L.negf_last_error()
+    n[1] = 10
+    rc = L.negf_sigma2b_batched(C.c_void_p(1), 2, n, 5, sg, ptrs, ptrs, ptrs, 0, None)
+    assert rc == negf.EINVAL and b"alias" in L.negf_last_error()
+    rc = L.negf_sigma2b_batched(C.c_void_p(1), 0, n, 5, sg, ptrs, ptrs, outs, 0, None)
+    assert rc == negf.EINVAL
+    rc = L.negf_sigma2b_batched_set_config(C.c_void_p(1), 2, n, 0, 6)
+    assert rc == negf.EINVAL
+    rc = L.negf_hf_batched(C.c_void_p(1), 0, 10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 2.0, 2, 10.0, 1e-10,
+                           10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None, None, None, None)
+    assert rc == negf.EINVAL
+
+
+def test_scf_batched_requires_one_tau_grid(L):
+    a, ka = negf.system_struct(W.config_he())
+    b, kb = negf.system_struct(W.config_he().with_(M=64))
+    arr = (negf.SystemT * 2)(a, b)
+    o = negf.OptsT(0.3, 1e-8, 10, 0, 0, 0, 1, 0.0, 0.0, 0)
+    rc = L.negf_scf_batched(C.c_void_p(1), 2, arr, C.byref(o), None, None, None, None, None, None, None, 0, None,
+                            None, None, None)
+    assert rc == negf.EINVAL and b"same tau grid" in L.negf_last_error()
