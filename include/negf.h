@@ -178,15 +178,17 @@ int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
  * per workgroup x column-chunk width) on the given input and stores the fastest
  * for (dtype, n_b) in the context; later negf_sigma2b calls with that dtype and
  * n_b use it. Arguments as for negf_sigma2b (Sigma_c is overwritten). *best
- * (host, nullable) receives the chosen index, ms (host, nullable, 6 entries) the
- * measured times (-1 for a configuration that does not fit). Synchronises. */
+ * (host, nullable) receives the chosen index, ms (host, nullable, 8 entries) the
+ * measured times (-1 for a configuration that does not fit or does not exist
+ * for this dtype). Synchronises. */
 int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
                       const void* G, void* Sigma_c, int dtype, int* best, double* ms, void* stream);
 
 /* Pin the negf_sigma2b tile configuration for (dtype, n_b) in this context:
  * 0..3 = (8 or 4 values of i per workgroup) x (208- or 112-column chunks) with
  * single-buffered k-panels; 4, 5 = 8 x 112 and 4 x 208 with double-buffered
- * k-panels. */
+ * k-panels; 6, 7 (NEGF_F32 and NEGF_BF16 only) = 4 waves with two values of i
+ * each x 112- or 64-column chunks. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
 /* Sigma-2B (as negf_sigma2b) for `batch` systems of any sizes n_b[b] on one
@@ -204,14 +206,14 @@ int negf_sigma2b_batched(negf_ctx* ctx, int batch, const int* n_b, int n_tau, co
                          const void* const* V, const void* const* G, void* const* Sigma_c,
                          int dtype, void* stream);
 
-/* Pin the negf_sigma2b_batched tile configuration (0..5, as negf_sigma2b_set_config)
+/* Pin the negf_sigma2b_batched tile configuration (0..7, as negf_sigma2b_set_config)
  * for this dtype and multiset of n_b (host, batch ints). */
 int negf_sigma2b_batched_set_config(negf_ctx* ctx, int batch, const int* n_b, int dtype, int cfg);
 
 /* Autotuner for negf_sigma2b_batched: times each tile configuration on the
  * first pair_lim slice pairs of every system (0: all pairs), keeps the fastest
  * for this dtype and multiset of n_b. Sigma_c is overwritten (partly). *best,
- * ms[6] (host, nullable) as for negf_sigma2b_tune. Synchronises. */
+ * ms[8] (host, nullable) as for negf_sigma2b_tune. Synchronises. */
 int negf_sigma2b_batched_tune(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
                               const void* const* V, const void* const* G, void* const* Sigma_c,
                               int dtype, int pair_lim, int* best, double* ms, void* stream);
@@ -345,7 +347,9 @@ int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* systems,
  * (Not in the paper: a production pattern around the method; the plain HF start remains
  * the fallback.) Features of a sample (i, j, tau): x_i/10, x_j/10, v(x_i), v(x_j),
  * Chebyshev T_0..T_15(2 tau/beta - 1), Z_1..Z_3, X_1/10..X_3/10 (nuclei zero-padded):
- * 26 numbers. Network 26 -> 256 -> 256 -> 256 -> 1, tanh on the hidden layers;
+ * 26 numbers. Network 26 -> 256 -> 256 -> 256 -> 1, tanh on the hidden layers; its
+ * output is multiplied by a fixed envelope (negf_mlp_envelope) that confines the
+ * correction to the neighbourhood of the nuclei and of tau = 0 and beta;
  * parameters are one float32 array in the order W1 (26 x 256, row-major, input-major),
  * b1, W2 (256 x 256), b2, W3, b3, W4 (256 x 1), b4. */
 int negf_mlp_param_count(int* count);
@@ -357,9 +361,19 @@ int negf_mlp_features(negf_ctx* ctx, int n_b, const double* x, const double* v, 
                       const double* Xc, const double* Zc, int n_tau, const double* tau, double beta,
                       int n_samples, const int* ii, const int* jj, const int* qq, float* F, void* stream);
 
-/* Training targets t[s] = (G[qq][ii][jj] - G0[qq][ii][jj]) / out_scale (dev). */
+/* Envelope of the learned correction at the samples (dev, float32):
+ * e(i, j, tau) = exp(-(d_i + d_j)/5 - min(tau, beta - tau)/10), d_i = distance of
+ * node x_i to the nearest of the n_c nuclei Xc (host; n_c = 0: d = 0). x, tau dev. */
+int negf_mlp_envelope(negf_ctx* ctx, const double* x, int n_c, const double* Xc, const double* tau,
+                      double beta, int n_samples, const int* ii, const int* jj, const int* qq,
+                      float* env, void* stream);
+
+/* Training targets t[s] = (G[qq][ii][jj] - G0[qq][ii][jj]) / (out_scale e(ii, jj, tau_qq))
+ * (dev), e the envelope of negf_mlp_envelope. */
 int negf_mlp_targets(negf_ctx* ctx, int n_b, const double* G, const double* G0, double out_scale,
-                     int n_samples, const int* ii, const int* jj, const int* qq, float* t, void* stream);
+                     const double* x, int n_c, const double* Xc, int n_tau, const double* tau,
+                     double beta, int n_samples, const int* ii, const int* jj, const int* qq,
+                     float* t, void* stream);
 
 /* Network output y[s] (dev, float32) for feature rows F (dev). */
 int negf_mlp_forward(negf_ctx* ctx, const float* params, int n_samples, const float* F, float* y,
@@ -375,7 +389,8 @@ int negf_mlp_train_step(negf_ctx* ctx, float* params, float* m, float* v, int st
                         double* loss, void* stream);
 
 /* Inference on the whole grid: for every q and i <= j, G_out[q][i][j] = G_out[q][j][i]
- * = (G0[q][i][j] + G0[q][j][i])/2 + out_scale y(i, j, tau_q). x, v, tau (dev, float64);
+ * = (G0[q][i][j] + G0[q][j][i])/2 + out_scale e(i, j, tau_q) y(i, j, tau_q), e the
+ * envelope of negf_mlp_envelope. x, v, tau (dev, float64);
  * G0, G_out (dev, float64 [n_tau][n_b][n_b]; may alias). */
 int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
                    const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,

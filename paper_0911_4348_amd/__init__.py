@@ -108,7 +108,9 @@ _SIGS = {
     "negf_mlp_param_count": (C.c_int, [_IP]),
     "negf_mlp_features": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP, C.c_double,
                                     C.c_int, _VP, _VP, _VP, _VP, _VP]),
-    "negf_mlp_targets": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_int, _VP, _VP, _VP, _VP, _VP]),
+    "negf_mlp_targets": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, _VP, C.c_int, _DP, C.c_int, _VP, C.c_double,
+                                   C.c_int, _VP, _VP, _VP, _VP, _VP]),
+    "negf_mlp_envelope": (C.c_int, [_VP, _VP, C.c_int, _DP, _VP, C.c_double, C.c_int, _VP, _VP, _VP, _VP, _VP]),
     "negf_mlp_forward": (C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     "negf_mlp_train_step": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, C.c_double, C.c_int, _VP, _VP, _VP, _DP,
                                       _VP]),
@@ -344,7 +346,7 @@ def sigma2b_tune(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=N
     if out is None:
         out = torch.empty_like(G)
     best = C.c_int()
-    ms = (C.c_double * 6)()
+    ms = (C.c_double * 8)()
     _check(lib().negf_sigma2b_tune(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
                                    _DT[dtype], C.byref(best), ms, _stream(stream)))
     return best.value, list(ms)
@@ -498,7 +500,7 @@ def sigma2b_batched_tune(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, pa
     Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
     Sp = (C.c_void_p * B)(*[_dev_ptr(o) for o in outs])
     best = C.c_int()
-    ms = np.zeros(6)
+    ms = np.zeros(8)
     _check(lib().negf_sigma2b_batched_tune(ctx.handle, B, n.ctypes.data_as(_IP), int(Gs[0].shape[0]),
                                            sg.ctypes.data_as(_IP), Vp, Gp, Sp, _DT[dtype], int(pair_lim),
                                            C.byref(best), _dptr(ms), _stream(stream)))
@@ -530,13 +532,26 @@ def mlp_features(ctx: Context, sysd, x_d, v_d, tau_d, ii, jj, qq, stream=None):
     return F
 
 
-def mlp_targets(ctx: Context, G, G0, out_scale, ii, jj, qq, stream=None):
+def mlp_targets(ctx: Context, sysd, x_d, tau_d, G, G0, out_scale, ii, jj, qq, stream=None):
+    """Enveloped training targets (G - G0) / (out_scale e) at the samples."""
     torch = _torch()
+    n_c, X, Z = _nuclei(sysd)
     S = ii.shape[0]
     t = torch.empty(S, dtype=torch.float32, device=G.device)
-    _check(lib().negf_mlp_targets(ctx.handle, G.shape[1], _dev_ptr(G), _dev_ptr(G0), float(out_scale), S,
+    _check(lib().negf_mlp_targets(ctx.handle, G.shape[1], _dev_ptr(G), _dev_ptr(G0), float(out_scale),
+                                  _dev_ptr(x_d), n_c, _dptr(X), tau_d.shape[0], _dev_ptr(tau_d), float(sysd.beta), S,
                                   _dev_ptr(ii), _dev_ptr(jj), _dev_ptr(qq), _dev_ptr(t), _stream(stream)))
     return t
+
+
+def mlp_envelope(ctx: Context, sysd, x_d, tau_d, ii, jj, qq, stream=None):
+    torch = _torch()
+    n_c, X, Z = _nuclei(sysd)
+    S = ii.shape[0]
+    e = torch.empty(S, dtype=torch.float32, device=x_d.device)
+    _check(lib().negf_mlp_envelope(ctx.handle, _dev_ptr(x_d), n_c, _dptr(X), _dev_ptr(tau_d), float(sysd.beta), S,
+                                   _dev_ptr(ii), _dev_ptr(jj), _dev_ptr(qq), _dev_ptr(e), _stream(stream)))
+    return e
 
 
 def mlp_forward(ctx: Context, params, F, stream=None):

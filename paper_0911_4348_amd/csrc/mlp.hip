@@ -1,6 +1,11 @@
 // Learned initial guess: a tau-resolved 4-layer MLP (float32) that predicts
 // dG_ij(tau) = G(tau) - G0(tau) from per-sample features; the guess is
 // G_init = G0 + (dG + dG^T)/2. Training and inference run in these kernels.
+// The network output y is scaled by a fixed envelope that localises the
+// correction where correlation lives, near the nuclei and near the ends of
+// [0, beta]: dG = s e(i, j, tau) y with
+//   e = exp(-(d_i + d_j)/L_X - min(tau, beta - tau)/L_T),
+// d_i the distance of node i to the nearest nucleus, L_X = 5, L_T = 10 (a.u.).
 //
 // Features per sample (i, j, tau): x_i/s, x_j/s, v_i, v_j, T_0..T_15(2 tau/beta - 1),
 // Z_1..Z_3, X_1/s..X_3/s (s = 10, nuclei zero-padded). Network 26 -> 256 -> 256 ->
@@ -29,10 +34,25 @@ inline unsigned grid_for(long total) {
     return (unsigned)b;
 }
 
+constexpr double ENV_LX = 5.0, ENV_LT = 10.0;
+
 struct NucTab {
     float Z[N_CENT];
     float X[N_CENT];
+    int n;
 };
+
+__device__ __forceinline__ double envelope(double xi, double xj, double tau, double beta, const NucTab& nt) {
+    double di = 0.0, dj = 0.0;
+    if (nt.n > 0) {
+        di = dj = 1e300;
+        for (int c = 0; c < nt.n; ++c) {
+            di = fmin(di, fabs(xi - (double)nt.X[c]));
+            dj = fmin(dj, fabs(xj - (double)nt.X[c]));
+        }
+    }
+    return exp(-(di + dj) / ENV_LX - fmin(tau, beta - tau) / ENV_LT);
+}
 
 __device__ __forceinline__ void feature_row(float* f, float xi, float xj, float vi, float vj, float t,
                                             const NucTab& nt) {
@@ -203,29 +223,34 @@ __global__ void k_tanh_grad(long tot, const float* a, float* d) {
     }
 }
 
-// g[c] = sum_s D[s][c] (bias gradients), one thread per column, fixed order
-__global__ void k_colsum(int S, int N, const float* D, float* g) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
+// Column reductions over the samples, in a fixed order (deterministic):
+// g[c] = sum_s D[s][c] * (w ? w[s] : 1) for c < N. Block (64 columns x 16 row
+// groups); each thread sums every 16th row of its column in double, then the 16
+// partial sums are added in order.
+__global__ __launch_bounds__(1024) void k_colsum(int S, int N, const float* __restrict__ D,
+                                                 const float* __restrict__ w, float* __restrict__ g) {
+    __shared__ double part[16][65];
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cx;
     double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += D[(long)s * N + c];
-    g[c] = (float)acc;
+    if (c < N) {
+        for (int s = ry; s < S; s += 16) acc += (double)D[(long)s * N + c] * (w ? (double)w[s] : 1.0);
+    }
+    part[ry][cx] = acc;
+    __syncthreads();
+    if (ry == 0 && c < N) {
+        double t = 0.0;
+        for (int r = 0; r < 16; ++r) t += part[r][cx];
+        g[c] = (float)t;
+    }
 }
 
-// gW4[k] = sum_s a3[s][k] dy[s]
-__global__ void k_gw4(int S, const float* a3, const float* dy, float* g) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= HID) return;
-    double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += (double)a3[(long)s * HID + k] * dy[s];
-    g[k] = (float)acc;
-}
-
-__global__ void k_sum_dy(int S, const float* dy, float* g) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double acc = 0.0;
-        for (int s = 0; s < S; ++s) acc += dy[s];
-        g[0] = (float)acc;
+// g[c] = sum_k P[k][c] over nsplit partial products (fixed order)
+__global__ void k_sum_partials(long count, int nsplit, const float* __restrict__ P, float* __restrict__ g) {
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < count; c += (long)gridDim.x * blockDim.x) {
+        float t = 0.f;
+        for (int k = 0; k < nsplit; ++k) t += P[(long)k * count + c];
+        g[c] = t;
     }
 }
 
@@ -242,24 +267,33 @@ __global__ void k_adam(long n, float* p, const float* g, float* m, float* v, flo
 }
 
 // targets t[s] = (G[q][i][j] - G0[q][i][j]) / scale
-__global__ void k_targets(int S, int n, const double* G, const double* G0, double scale, const int* ii, const int* jj,
-                          const int* qq, float* t) {
+__global__ void k_targets(int S, int n, const double* G, const double* G0, double scale, const double* x,
+                          const double* tau, double beta, NucTab nt, const int* ii, const int* jj, const int* qq,
+                          float* t) {
     const long nn = (long)n * n;
     for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
-        const long e = (long)qq[s] * nn + (long)ii[s] * n + jj[s];
-        t[s] = (float)((G[e] - G0[e]) / scale);
+        const int i = ii[s], j = jj[s], q = qq[s];
+        const long e = (long)q * nn + (long)i * n + j;
+        t[s] = (float)((G[e] - G0[e]) / (scale * envelope(x[i], x[j], tau[q], beta, nt)));
     }
 }
 
+__global__ void k_envelope(int S, const double* x, const double* tau, double beta, NucTab nt, const int* ii,
+                           const int* jj, const int* qq, float* env) {
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x)
+        env[s] = (float)envelope(x[ii[s]], x[jj[s]], tau[qq[s]], beta, nt);
+}
+
 // G_out[q][i][j] = G_out[q][j][i] = G0[q][i][j] + scale y  for the range's samples
-__global__ void k_scatter_guess(int n, long g0, long S, const float* y, double scale, const double* G0, double* Gout) {
+__global__ void k_scatter_guess(int n, long g0, long S, const float* y, double scale, const double* x,
+                                const double* tau, double beta, NucTab nt, const double* G0, double* Gout) {
     const long P = (long)n * (n + 1) / 2, nn = (long)n * n;
     for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
         const long g = g0 + s;
         const int q = (int)(g / P);
         int i, j;
         pair_of(n, g % P, &i, &j);
-        const double d = scale * (double)y[s];
+        const double d = scale * envelope(x[i], x[j], tau[q], beta, nt) * (double)y[s];
         const long a = (long)q * nn + (long)i * n + j, b = (long)q * nn + (long)j * n + i;
         // symmetric average of the two G0 entries keeps the guess exactly symmetric
         const double base = 0.5 * (G0[a] + G0[b]);
@@ -270,6 +304,7 @@ __global__ void k_scatter_guess(int n, long g0, long S, const float* y, double s
 
 NucTab make_nuc(int n_c, const double* X, const double* Z) {
     NucTab t{};
+    t.n = n_c < N_CENT ? n_c : N_CENT;
     for (int c = 0; c < N_CENT; ++c) {
         t.Z[c] = c < n_c ? (float)Z[c] : 0.f;
         t.X[c] = c < n_c ? (float)X[c] : 0.f;
@@ -320,12 +355,29 @@ extern "C" int negf_mlp_features(negf_ctx* ctx, int n_b, const double* x, const 
 }
 
 extern "C" int negf_mlp_targets(negf_ctx* ctx, int n_b, const double* G, const double* G0, double out_scale,
+                                const double* x, int n_c, const double* Xc, int n_tau, const double* tau, double beta,
                                 int n_samples, const int* ii, const int* jj, const int* qq, float* t, void* stream) {
-    NEGF_REQUIRE(ctx && G && G0 && ii && jj && qq && t, "NULL argument");
-    NEGF_REQUIRE(n_b >= 1 && n_samples >= 1 && out_scale > 0, "bad sizes");
+    NEGF_REQUIRE(ctx && G && G0 && x && tau && ii && jj && qq && t, "NULL argument");
+    NEGF_REQUIRE(n_b >= 1 && n_samples >= 1 && out_scale > 0 && n_tau >= 2 && beta > 0, "bad sizes");
+    NEGF_REQUIRE(n_c >= 0 && n_c <= N_CENT && (n_c == 0 || Xc), "n_c must be 0..3");
     NEGF_TRY(bind_device(ctx));
+    std::vector<double> zz(N_CENT, 0.0);
     hipLaunchKernelGGL(k_targets, dim3(grid_for(n_samples)), dim3(256), 0, (hipStream_t)stream, n_samples, n_b, G, G0,
-                       out_scale, ii, jj, qq, t);
+                       out_scale, x, tau, beta, make_nuc(n_c, Xc, zz.data()), ii, jj, qq, t);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
+extern "C" int negf_mlp_envelope(negf_ctx* ctx, const double* x, int n_c, const double* Xc, const double* tau,
+                                 double beta, int n_samples, const int* ii, const int* jj, const int* qq, float* env,
+                                 void* stream) {
+    NEGF_REQUIRE(ctx && x && tau && ii && jj && qq && env, "NULL argument");
+    NEGF_REQUIRE(n_samples >= 1 && beta > 0, "bad sizes");
+    NEGF_REQUIRE(n_c >= 0 && n_c <= N_CENT && (n_c == 0 || Xc), "n_c must be 0..3");
+    NEGF_TRY(bind_device(ctx));
+    std::vector<double> zz(N_CENT, 0.0);
+    hipLaunchKernelGGL(k_envelope, dim3(grid_for(n_samples)), dim3(256), 0, (hipStream_t)stream, n_samples, x, tau,
+                       beta, make_nuc(n_c, Xc, zz.data()), ii, jj, qq, env);
     LAUNCH_CHECK();
     return NEGF_OK;
 }
@@ -360,35 +412,57 @@ extern "C" int negf_mlp_train_step(negf_ctx* ctx, float* params, float* m, float
     NEGF_TRY(forward(ctx, S, F, params, &a1, &a2, &a3, y, st));
     hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, st, S, y, target, dy, part);
     LAUNCH_CHECK();
-    // output layer
-    hipLaunchKernelGGL(k_gw4, dim3(1), dim3(HID), 0, st, S, a3, dy, g + OFF_W4);
+    // weight gradients A^T D over the samples, split into NS sample ranges
+    // (batched products into partial buffers, then a fixed-order sum)
+    constexpr int NS = 16;
+    float* wpart;
+    NEGF_TRY(scratch_t(ctx, "mlp_wpart", (size_t)(NS + 1) * HID * HID, &wpart));
+    auto wgrad = [&](const float* A, int K, const float* Dm, float* out) -> int {
+        const int c = S / NS, r = S - NS * c;
+        int np = 0;
+        if (c > 0) {
+            NEGF_TRY(gemm<float>(st, true, false, K, HID, c, 1.f, A, K, (long)c * K, Dm, HID, (long)c * HID, 0.f,
+                                 nullptr, 0, 0, wpart, HID, (long)K * HID, NS));
+            np = NS;
+        }
+        if (r > 0) {
+            NEGF_TRY(gemm<float>(st, true, false, K, HID, r, 1.f, A + (long)NS * c * K, K, 0,
+                                 Dm + (long)NS * c * HID, HID, 0, 0.f, nullptr, 0, 0, wpart + (long)np * K * HID,
+                                 HID, 0, 1));
+            ++np;
+        }
+        hipLaunchKernelGGL(k_sum_partials, dim3(grid_for((long)K * HID)), dim3(256), 0, st, (long)K * HID, np, wpart,
+                           out);
+        LAUNCH_CHECK();
+        return NEGF_OK;
+    };
+    const unsigned cb = (HID + 63) / 64;
+    // output layer: gW4 = a3^T dy, gb4 = sum dy
+    hipLaunchKernelGGL(k_colsum, dim3(cb), dim3(1024), 0, st, S, HID, a3, dy, g + OFF_W4);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_dy, dim3(1), dim3(64), 0, st, S, dy, g + OFF_B4);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1024), 0, st, S, 1, dy, nullptr, g + OFF_B4);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_back_out, dim3(grid_for((long)S * HID)), dim3(256), 0, st, S, dy, params + OFF_W4, a3, d3);
     LAUNCH_CHECK();
     // layer 3: gW3 = a2^T d3, gb3 = colsum d3, d2 = (d3 W3^T) o (1 - a2^2)
-    NEGF_TRY(gemm<float>(st, true, false, HID, HID, S, 1.f, a2, HID, 0, d3, HID, 0, 0.f, nullptr, 0, 0, g + OFF_W3, HID,
-                         0, 1));
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(HID), 0, st, S, HID, d3, g + OFF_B3);
+    NEGF_TRY(wgrad(a2, HID, d3, g + OFF_W3));
+    hipLaunchKernelGGL(k_colsum, dim3(cb), dim3(1024), 0, st, S, HID, d3, nullptr, g + OFF_B3);
     LAUNCH_CHECK();
     NEGF_TRY(gemm<float>(st, false, true, S, HID, HID, 1.f, d3, HID, 0, params + OFF_W3, HID, 0, 0.f, nullptr, 0, 0, d2,
                          HID, 0, 1));
     hipLaunchKernelGGL(k_tanh_grad, dim3(grid_for((long)S * HID)), dim3(256), 0, st, (long)S * HID, a2, d2);
     LAUNCH_CHECK();
     // layer 2: gW2 = a1^T d2, gb2, d1 = (d2 W2^T) o (1 - a1^2)   (d1 reuses d3)
-    NEGF_TRY(gemm<float>(st, true, false, HID, HID, S, 1.f, a1, HID, 0, d2, HID, 0, 0.f, nullptr, 0, 0, g + OFF_W2, HID,
-                         0, 1));
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(HID), 0, st, S, HID, d2, g + OFF_B2);
+    NEGF_TRY(wgrad(a1, HID, d2, g + OFF_W2));
+    hipLaunchKernelGGL(k_colsum, dim3(cb), dim3(1024), 0, st, S, HID, d2, nullptr, g + OFF_B2);
     LAUNCH_CHECK();
     NEGF_TRY(gemm<float>(st, false, true, S, HID, HID, 1.f, d2, HID, 0, params + OFF_W2, HID, 0, 0.f, nullptr, 0, 0, d3,
                          HID, 0, 1));
     hipLaunchKernelGGL(k_tanh_grad, dim3(grid_for((long)S * HID)), dim3(256), 0, st, (long)S * HID, a1, d3);
     LAUNCH_CHECK();
     // layer 1: gW1 = F^T d1, gb1
-    NEGF_TRY(gemm<float>(st, true, false, D_IN, HID, S, 1.f, F, D_IN, 0, d3, HID, 0, 0.f, nullptr, 0, 0, g + OFF_W1, HID,
-                         0, 1));
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(HID), 0, st, S, HID, d3, g + OFF_B1);
+    NEGF_TRY(wgrad(F, D_IN, d3, g + OFF_W1));
+    hipLaunchKernelGGL(k_colsum, dim3(cb), dim3(1024), 0, st, S, HID, d3, nullptr, g + OFF_B1);
     LAUNCH_CHECK();
     if (grad_out) HIP_TRY(hipMemcpyAsync(grad_out, g, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice, st));
     if (lr > 0) {
@@ -430,7 +504,8 @@ extern "C" int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_sca
         LAUNCH_CHECK();
         float *a1, *a2, *a3;
         NEGF_TRY(forward(ctx, (int)S, F, params, &a1, &a2, &a3, y, st));
-        hipLaunchKernelGGL(k_scatter_guess, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, y, out_scale, G0, G_out);
+        hipLaunchKernelGGL(k_scatter_guess, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, y, out_scale, x, tau, beta,
+                           nt, G0, G_out);
         LAUNCH_CHECK();
     }
     return NEGF_OK;

@@ -57,13 +57,14 @@ constexpr size_t stage_bytes() {
     return ((b > v ? b : v) + 15) & ~size_t(15);
 }
 
-template <int MODE, int IB, int JB, bool DB>
+template <int MODE, int IB, int JB, bool DB, int IPW>
 constexpr size_t lds_bytes(int np) {
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
+    constexpr int IR = IB * IPW;
     const int npj = (np + JB * 16 - 1) / (JB * 16) * (JB * 16);
     return (DB ? 2 : 1) * stage_bytes<MODE, JB>() +
-           sizeof(T) * (2 * 16 * (BK + 1) + 2 * IB * BK + (size_t)IB * (3 * np + npj));
+           sizeof(T) * (2 * 16 * (BK + 1) + 2 * IR * BK + (size_t)IR * (3 * np + npj));
 }
 
 // Workgroups are handed to the 8 XCDs round-robin by block index; renumber them
@@ -76,9 +77,10 @@ __device__ __forceinline__ long xcd_remap(long b, long nb) {
 }
 
 // minimum waves per SIMD the register allocation must allow for a configuration
-template <int MODE, int IB, int JB, bool DB>
+template <int MODE, int IB, int JB, bool DB, int IPW>
 constexpr int waves_per_eu() {
     // chosen so that every configuration compiles without register spills
+    if (IPW > 1) return JB > 4 ? 2 : 3;
     if (MODE == MODE_F64) return JB > 8 ? (IB == 4 ? 1 : 2) : 2;
     if (MODE == MODE_BF16) return JB > 8 ? (IB == 4 ? 1 : 2) : (DB ? 2 : (IB == 4 ? 2 : 4));
     return JB > 8 ? (IB == 4 && DB ? 1 : 2) : (DB ? 3 : 4);
@@ -88,7 +90,10 @@ constexpr int waves_per_eu() {
 // are double-buffered: while the matrix cores work on panel p from LDS, the
 // loads of panel p+1 are in flight into registers, then written to the other
 // LDS buffer; one barrier per panel.
-template <int MODE, int IB, int JB, bool DB>
+// IPW values of i per wave (IB * IPW per workgroup): with IPW = 2 every B
+// fragment read from LDS feeds two matrix-core operations, which halves the
+// LDS traffic per flop where that traffic, not the matrix cores, is the limit.
+template <int MODE, int IB, int JB, bool DB, int IPW>
 __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, typename Cfg<MODE>::T sigma,
                                          const typename Cfg<MODE>::T* __restrict__ V,
                                          const typename Cfg<MODE>::T* __restrict__ G, const int* __restrict__ ex,
@@ -96,6 +101,7 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
     constexpr int NT = IB * 64;
+    constexpr int IR = IB * IPW;                 // rows i per workgroup
     constexpr int GS_LD = JB * 16 + 1;
     // B-panel staging: thread t owns column t % CW of the chunk and rows
     // t / CW + RP r of the panel (r < NSLOT)
@@ -106,13 +112,13 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
     constexpr size_t SB = stage_bytes<MODE, JB>();
     unsigned char* stage0 = smem_raw;
     T* Abuf = reinterpret_cast<T*>(smem_raw + (DB ? 2 : 1) * SB);         // [2][16][BK + 1]
-    T* Vbuf = Abuf + 2 * 16 * (BK + 1);                                   // [2][IB][BK]
+    T* Vbuf = Abuf + 2 * 16 * (BK + 1);                                   // [2][IR][BK]
     const int np = (n + 15) & ~15;
     const int npj = (np + JB * 16 - 1) / (JB * 16) * (JB * 16);          // np padded to whole chunks
-    T* T1s = Vbuf + 2 * IB * BK;                                          // [IB][np]  diag of M^(i)
-    T* Xs = T1s + IB * np;                                                // [IB][np]  X  (slice q)
-    T* XPs = Xs + IB * np;                                                // [IB][np]  X' (slice q')
-    T* Gbi = XPs + IB * np;                                               // [IB][npj] row i of Gb (scaled)
+    T* T1s = Vbuf + 2 * IR * BK;                                          // [IR][np]  diag of M^(i)
+    T* Xs = T1s + IR * np;                                                // [IR][np]  X  (slice q)
+    T* XPs = Xs + IR * np;                                                // [IR][np]  X' (slice q')
+    T* Gbi = XPs + IR * np;                                               // [IR][npj] row i of Gb (scaled)
     T* Vt = reinterpret_cast<T*>(stage0);                                 // V tile [16][GS_LD] (buffer 0)
 
     // opaque copy of the thread index: in the persistent kernel this keeps the
@@ -127,8 +133,7 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
     const T* Gb = G + (long)qb * nn;
     T* Sq = Sc + (long)q * nn;
     T* Sqb = Sc + (long)qb * nn;
-    const int i = iblk * IB + w;
-    const bool iok = i < n;
+    // this wave's rows: r = w * IPW + p, i = iblk * IR + r
     const int lc = lane & 15, lg = lane >> 4;
     T sq = T(1), sqb = T(1), uq = T(1), uqb = T(1);
     if constexpr (MODE != MODE_F64) {
@@ -138,34 +143,37 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
         uqb = (T)ldexpf(1.0f, -(ex[q] + 2 * ex[qb]));
     }
 
-    for (int e = tid; e < 3 * IB * np; e += NT) T1s[e] = T(0);     // T1s, Xs, XPs
-    for (int e = tid; e < IB * npj; e += NT) {
-        const int ww = e / npj, j = e - ww * npj;
-        const int ii = iblk * IB + ww;
+    for (int e = tid; e < 3 * IR * np; e += NT) T1s[e] = T(0);     // T1s, Xs, XPs
+    for (int e = tid; e < IR * npj; e += NT) {
+        const int rr = e / npj, j = e - rr * npj;
+        const int ii = iblk * IR + rr;
         Gbi[e] = (ii < n && j < n) ? Gb[(long)ii * n + j] * sqb : T(0);
     }
     // A-operand staging: element tid + NT r of the [16][BK] panel, r < RA
     constexpr int RA = (16 * BK + NT - 1) / NT;
-    static_assert(IB * BK <= NT, "one V_i element per thread");
-    const int v_w = tid / BK, v_kk = tid - v_w * BK;                      // valid for tid < IB BK
-    const int v_i = iblk * IB + v_w;
+    // V_i staging: element tid + NT r of the [IR][BK] panel, r < RV
+    constexpr int RV = (IR * BK + NT - 1) / NT;
 
     for (int j0 = 0; j0 < np; j0 += JB * 16) {
         const int njb = min(JB, (np - j0) >> 4);
         const int jw = njb * 16;
         const int s_jj = tid % CW, s_kk = tid / CW;
         const bool s_col = s_jj < jw && j0 + s_jj < n;
-        T xcol[JB];
+        T xcol[IPW][JB];
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb) xcol[jb] = T(0);
+        for (int p = 0; p < IPW; ++p)
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) xcol[p][jb] = T(0);
 
         constexpr int NJB = JB;   // the last chunk is padded with zero columns
 #pragma unroll 1
         for (int l0 = 0; l0 < n; l0 += 16) {
-            typename Mma<T>::acc_t acc[NJB];
+            typename Mma<T>::acc_t acc[IPW][NJB];
 #pragma unroll
-            for (int jb = 0; jb < NJB; ++jb) acc[jb] = Mma<T>::zero();
-            T rg[NSLOT], ra[RA], rv = T(0);
+            for (int p = 0; p < IPW; ++p)
+#pragma unroll
+                for (int jb = 0; jb < NJB; ++jb) acc[p][jb] = Mma<T>::zero();
+            T rg[NSLOT], ra[RA], rv[RV];
             auto load = [&](int k0) {
 #pragma unroll
                 for (int r = 0; r < NSLOT; ++r) {
@@ -178,9 +186,11 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                     const int l = l0 + ll, k = k0 + kk;
                     ra[r] = (e < 16 * BK && l < n && k < n) ? Gb[(long)l * n + k] : T(0);
                 }
-                if (tid < IB * BK) {
-                    const int k = k0 + v_kk;
-                    rv = (v_i < n && k < n) ? V[(long)v_i * n + k] : T(0);
+#pragma unroll
+                for (int r = 0; r < RV; ++r) {
+                    const int e = tid + NT * r, rr = e / BK, kk = e - rr * BK;
+                    const int vi = iblk * IR + rr, k = k0 + kk;
+                    rv[r] = (e < IR * BK && vi < n && k < n) ? V[(long)vi * n + k] : T(0);
                 }
             };
             auto store = [&](int buf) {
@@ -200,7 +210,11 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                     const int e = tid + NT * r, ll = e / BK, kk = e - ll * BK;
                     if (e < 16 * BK) Abuf[buf * 16 * (BK + 1) + ll * (BK + 1) + kk] = ra[r] * sqb;
                 }
-                if (tid < IB * BK) Vbuf[buf * IB * BK + tid] = rv;
+#pragma unroll
+                for (int r = 0; r < RV; ++r) {
+                    const int e = tid + NT * r;
+                    if (e < IR * BK) Vbuf[buf * IR * BK + e] = rv[r];
+                }
             };
             const int npan = (n + BK - 1) / BK;
             if constexpr (DB) {
@@ -210,41 +224,52 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                 __syncthreads();
             }
 #pragma unroll 1
-            for (int p = 0; p < npan; ++p) {
-                const int buf = DB ? (p & 1) : 0;
-                const bool more = DB && p + 1 < npan;
+            for (int pn = 0; pn < npan; ++pn) {
+                const int buf = DB ? (pn & 1) : 0;
+                const bool more = DB && pn + 1 < npan;
                 if constexpr (!DB) {
-                    load(p * BK);
+                    load(pn * BK);
                     __syncthreads();
                     store(0);
                     __syncthreads();
                 }
-                if (more) load((p + 1) * BK);
+                if (more) load((pn + 1) * BK);
                 const T* Ab = Abuf + buf * 16 * (BK + 1);
-                const T* Vk = Vbuf + buf * IB * BK;
+                const T* Vk = Vbuf + buf * IR * BK;
                 if constexpr (MODE == MODE_BF16) {
                     const __bf16* Bt = reinterpret_cast<const __bf16*>(stage0 + buf * SB);
-                    bf16x8 a;
+                    bf16x8 a[IPW];
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int kk = lg * 8 + e;
-                        a[e] = (__bf16)(float)(Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk]);
+                        const T av = Ab[lc * (BK + 1) + kk];
+#pragma unroll
+                        for (int p = 0; p < IPW; ++p) a[p][e] = (__bf16)(float)(av * Vk[(w * IPW + p) * BK + kk]);
                     }
 #pragma unroll
                     for (int jb = 0; jb < NJB; ++jb) {
                         const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[(jb * 16 + lc) * BT_LD + lg * 8]);
-                        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jb], 0, 0, 0);
+#pragma unroll
+                        for (int p = 0; p < IPW; ++p)
+                            acc[p][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[p], b, acc[p][jb], 0, 0, 0);
                     }
                 } else {
                     const T* Gs = reinterpret_cast<const T*>(stage0 + buf * SB);
                     // k-steps of 4 that hold real rows (uniform across the workgroup)
-                    const int nks = min(BK / 4, (n - p * BK + 3) >> 2);
+                    const int nks = min(BK / 4, (n - pn * BK + 3) >> 2);
 #pragma unroll 4
                     for (int ks = 0; ks < nks; ++ks) {
                         const int kk = ks * 4 + lg;
-                        const T a = Ab[lc * (BK + 1) + kk] * Vk[w * BK + kk];
+                        const T av = Ab[lc * (BK + 1) + kk];
+                        T a[IPW];
 #pragma unroll
-                        for (int jb = 0; jb < NJB; ++jb) acc[jb] = Mma<T>::mma(a, Gs[kk * GS_LD + jb * 16 + lc], acc[jb]);
+                        for (int p = 0; p < IPW; ++p) a[p] = av * Vk[(w * IPW + p) * BK + kk];
+#pragma unroll
+                        for (int jb = 0; jb < NJB; ++jb) {
+                            const T bv = Gs[kk * GS_LD + jb * 16 + lc];
+#pragma unroll
+                            for (int p = 0; p < IPW; ++p) acc[p][jb] = Mma<T>::mma(a[p], bv, acc[p][jb]);
+                        }
                     }
                 }
                 if constexpr (DB) {
@@ -260,8 +285,10 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                 for (int jb = 0; jb < NJB; ++jb)
                     if (jb == jd) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (Mma<T>::row(lane, r) == lc) T1s[w * np + l0 + lc] = acc[jb][r];
+                        for (int p = 0; p < IPW; ++p)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (Mma<T>::row(lane, r) == lc) T1s[(w * IPW + p) * np + l0 + lc] = acc[p][jb][r];
                     }
             }
             // V rows l0..l0+15 (this chunk's columns, zero-padded) into buffer 0
@@ -271,45 +298,54 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                 Vt[ll * GS_LD + jj] = (l < n && jj < jw && j < n) ? V[(long)l * n + j] : T(0);
             }
             __syncthreads();
-            T gil[4], xp[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int l = l0 + Mma<T>::row(lane, r);
-                gil[r] = (iok && l < n) ? Gq[(long)i * n + l] * sq : T(0);
-                xp[r] = T(0);
-            }
-#pragma unroll
-            for (int jb = 0; jb < NJB; ++jb) {
+            for (int p = 0; p < IPW; ++p) {
+                const int rr = w * IPW + p, i = iblk * IR + rr;
+                const bool iok = i < n;
+                T gil[4], xp[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const T vm = Vt[Mma<T>::row(lane, r) * GS_LD + jb * 16 + lc] * acc[jb][r];
-                    xp[r] += Gbi[w * npj + j0 + jb * 16 + lc] * vm;
-                    xcol[jb] += gil[r] * vm;
+                    const int l = l0 + Mma<T>::row(lane, r);
+                    gil[r] = (iok && l < n) ? Gq[(long)i * n + l] * sq : T(0);
+                    xp[r] = T(0);
                 }
-            }
-            // X'_il (slice q'), partial over this chunk's columns
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const T sx = sum16(xp[r]);
-                const int l = l0 + Mma<T>::row(lane, r);
-                if (lc == 0) XPs[w * np + l] += sx;
+                for (int jb = 0; jb < NJB; ++jb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const T vm = Vt[Mma<T>::row(lane, r) * GS_LD + jb * 16 + lc] * acc[p][jb][r];
+                        xp[r] += Gbi[rr * npj + j0 + jb * 16 + lc] * vm;
+                        xcol[p][jb] += gil[r] * vm;
+                    }
+                }
+                // X'_il (slice q'), partial over this chunk's columns
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T sx = sum16(xp[r]);
+                    const int l = l0 + Mma<T>::row(lane, r);
+                    if (lc == 0) XPs[rr * np + l] += sx;
+                }
             }
         }
         // X_ij (slice q) for this chunk's columns
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb) {
-            const T sx = sum4x16(xcol[jb]);
-            if (jb < njb && lg == 0) Xs[w * np + j0 + jb * 16 + lc] = sx;
-        }
+        for (int p = 0; p < IPW; ++p)
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                const T sx = sum4x16(xcol[p][jb]);
+                if (jb < njb && lg == 0) Xs[(w * IPW + p) * np + j0 + jb * 16 + lc] = sx;
+            }
     }
 
     // direct term D_ij = sum_l T1_il V_lj, then one store per output element
     constexpr int DM = (JB * 16 + 63) / 64;
     for (int j0 = 0; j0 < np; j0 += JB * 16) {
         const int jw = min(JB * 16, np - j0);
-        T d[DM];
+        T d[IPW][DM];
 #pragma unroll
-        for (int m = 0; m < DM; ++m) d[m] = T(0);
+        for (int p = 0; p < IPW; ++p)
+#pragma unroll
+            for (int m = 0; m < DM; ++m) d[p][m] = T(0);
         for (int l0 = 0; l0 < n; l0 += 16) {
             __syncthreads();
             for (int e = tid; e < 16 * jw; e += NT) {
@@ -319,20 +355,27 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
             }
             __syncthreads();
             for (int ll = 0; ll < 16; ++ll) {
-                const T t = (l0 + ll < n) ? T1s[w * np + l0 + ll] : T(0);
 #pragma unroll
-                for (int m = 0; m < DM; ++m)
-                    if (lane + 64 * m < jw) d[m] += t * Vt[ll * GS_LD + lane + 64 * m];
+                for (int p = 0; p < IPW; ++p) {
+                    const T t = (l0 + ll < n) ? T1s[(w * IPW + p) * np + l0 + ll] : T(0);
+#pragma unroll
+                    for (int m = 0; m < DM; ++m)
+                        if (lane + 64 * m < jw) d[p][m] += t * Vt[ll * GS_LD + lane + 64 * m];
+                }
             }
         }
-        if (iok) {
 #pragma unroll
-            for (int m = 0; m < DM; ++m) {
-                const int j = j0 + lane + 64 * m;
-                if (lane + 64 * m < jw && j < n) {
-                    const long ij = (long)i * n + j;
-                    Sq[ij] = (sigma * (Gq[ij] * sq) * d[m] - Xs[w * np + j]) * uq;
-                    if (!middle) Sqb[ij] = (sigma * (Gb[ij] * sqb) * d[m] - XPs[w * np + j]) * uqb;
+        for (int p = 0; p < IPW; ++p) {
+            const int rr = w * IPW + p, i = iblk * IR + rr;
+            if (i < n) {
+#pragma unroll
+                for (int m = 0; m < DM; ++m) {
+                    const int j = j0 + lane + 64 * m;
+                    if (lane + 64 * m < jw && j < n) {
+                        const long ij = (long)i * n + j;
+                        Sq[ij] = (sigma * (Gq[ij] * sq) * d[p][m] - Xs[rr * np + j]) * uq;
+                        if (!middle) Sqb[ij] = (sigma * (Gb[ij] * sqb) * d[p][m] - XPs[rr * np + j]) * uqb;
+                    }
                 }
             }
         }
@@ -340,13 +383,13 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
 }
 
 // One workgroup per (slice pair, block of IB rows i), XCD-aware block order.
-template <int MODE, int IB, int JB, bool DB>
-__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k_sigma2b(
+template <int MODE, int IB, int JB, bool DB, int IPW>
+__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) void k_sigma2b(
     int n, int n_tau, int n_iblk, typename Cfg<MODE>::T sigma, const typename Cfg<MODE>::T* __restrict__ V,
     const typename Cfg<MODE>::T* __restrict__ G, const int* __restrict__ ex, typename Cfg<MODE>::T* __restrict__ Sc) {
     extern __shared__ unsigned char smem_raw[];
     const long lb = xcd_remap(blockIdx.x, gridDim.x);
-    s2b_tile<MODE, IB, JB, DB>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, ex, Sc, smem_raw);
+    s2b_tile<MODE, IB, JB, DB, IPW>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, ex, Sc, smem_raw);
 }
 
 // One system of a batch for the persistent kernel. Its work items are
@@ -373,8 +416,8 @@ struct XcdCuts {
 // and so that XCD's L2), then steals from the other queues until all eight
 // are empty. heads[0..7] count taken items per queue and must be zero at
 // launch. Every workgroup leaves after eight failed probes.
-template <int MODE, int IB, int JB, bool DB>
-__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k_sigma2b_batched(
+template <int MODE, int IB, int JB, bool DB, int IPW>
+__global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) void k_sigma2b_batched(
     const S2BInst<typename Cfg<MODE>::T>* __restrict__ inst, int n_inst, int n_tau, XcdCuts cuts, int* heads) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ long s_item;
@@ -401,7 +444,7 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB>())) void k
         }
         const long local = it - inst[lo].item0;
         const int nib = inst[lo].n_iblk;
-        s2b_tile<MODE, IB, JB, DB>(inst[lo].n, n_tau, (int)(local / nib), (int)(local % nib), inst[lo].sigma,
+        s2b_tile<MODE, IB, JB, DB, IPW>(inst[lo].n, n_tau, (int)(local / nib), (int)(local % nib), inst[lo].sigma,
                                    inst[lo].V, inst[lo].G, inst[lo].ex, inst[lo].Sc, smem_raw);
     }
 }
@@ -437,22 +480,21 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
     }
 }
 
-// Tile configurations the tuner chooses from: waves (values of i) per
-// workgroup and 16-wide column blocks per chunk.
+// Tile configurations the tuner chooses from: waves per workgroup (one value
+// of i each unless noted) and 16-wide column blocks per chunk.
 // 0: 8 x 208 cols, 1: 8 x 112, 2: 4 x 208, 3: 4 x 112 (single-buffered staging);
-// 4: 8 x 112, 5: 4 x 208 (double-buffered staging).
-constexpr int kNumCfg = 6;
+// 4: 8 x 112, 5: 4 x 208 (double-buffered staging);
+// 6: 4 waves x 2 values of i x 112 cols, 7: 4 x 2 x 64 cols (float32 and bf16 only).
+constexpr int kNumCfg = 8;
 
-template <int MODE, int IB, int JB, bool DB>
+template <int MODE, int IB, int JB, bool DB, int IPW>
 int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, const typename Cfg<MODE>::T* G,
                const int* ex, typename Cfg<MODE>::T* Sc, hipStream_t st) {
     typedef typename Cfg<MODE>::T T;
     const int n_pairs = (n_tau + 1) / 2;
-    const int n_iblk = (n + IB - 1) / IB;
+    const int n_iblk = (n + IB * IPW - 1) / (IB * IPW);
     const int np = (n + 15) & ~15;
-    constexpr int BK = Cfg<MODE>::BK;
-    (void)BK;
-    const size_t smem = lds_bytes<MODE, IB, JB, DB>(np);
+    const size_t smem = lds_bytes<MODE, IB, JB, DB, IPW>(np);
     if (smem > 160 * 1024) {
         set_error("n_b = %d too large for the Sigma-2B kernel's LDS budget", n);
         return NEGF_EINVAL;
@@ -464,11 +506,11 @@ int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, cons
     }
     static bool attr_set = false;
     if (!attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB, JB, DB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    160 * 1024));
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b<MODE, IB, JB, DB, IPW>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sigma2b<MODE, IB, JB, DB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
+    hipLaunchKernelGGL((k_sigma2b<MODE, IB, JB, DB, IPW>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
                        T(sigma), V, G, ex, Sc);
     LAUNCH_CHECK();
     return NEGF_OK;
@@ -484,12 +526,20 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
         LAUNCH_CHECK();
     }
     switch (cfg) {
-        case 0: return launch_cfg<MODE, 8, 13, false>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 1: return launch_cfg<MODE, 8, 7, false>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 2: return launch_cfg<MODE, 4, 13, false>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 3: return launch_cfg<MODE, 4, 7, false>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 4: return launch_cfg<MODE, 8, 7, true>(n, n_tau, sigma, V, G, ex, Sc, st);
-        default: return launch_cfg<MODE, 4, 13, true>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 0: return launch_cfg<MODE, 8, 13, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 1: return launch_cfg<MODE, 8, 7, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 2: return launch_cfg<MODE, 4, 13, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 3: return launch_cfg<MODE, 4, 7, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 4: return launch_cfg<MODE, 8, 7, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 5: return launch_cfg<MODE, 4, 13, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        default:
+            if constexpr (MODE == MODE_F64) {
+                set_error("tile configuration %d is for float32 and bf16 only", cfg);
+                return NEGF_EINVAL;
+            } else {
+                if (cfg == 6) return launch_cfg<MODE, 4, 7, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
+                return launch_cfg<MODE, 4, 4, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
+            }
     }
 }
 
@@ -584,16 +634,16 @@ int sigma2b_tune(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T
 // ============================================================== batched (persistent) form
 namespace {
 
-template <int MODE, int IB, int JB, bool DB>
+template <int MODE, int IB, int JB, bool DB, int IPW>
 int launch_batched_cfg(const S2BBatch& pl, hipStream_t st) {
     typedef typename Cfg<MODE>::T T;
     const int np = (pl.max_n + 15) & ~15;
-    const size_t smem = lds_bytes<MODE, IB, JB, DB>(np);
+    const size_t smem = lds_bytes<MODE, IB, JB, DB, IPW>(np);
     if (smem + 64 > 160 * 1024) {
         set_error("n_b = %d too large for this Sigma-2B tile configuration's LDS budget", pl.max_n);
         return NEGF_EINVAL;
     }
-    auto kern = k_sigma2b_batched<MODE, IB, JB, DB>;
+    auto kern = k_sigma2b_batched<MODE, IB, JB, DB, IPW>;
     static bool attr_set = false;
     if (!attr_set) {
         HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64));
@@ -621,16 +671,25 @@ int launch_batched_cfg(const S2BBatch& pl, hipStream_t st) {
 template <int MODE>
 int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
     switch (cfg) {
-        case 0: return launch_batched_cfg<MODE, 8, 13, false>(pl, st);
-        case 1: return launch_batched_cfg<MODE, 8, 7, false>(pl, st);
-        case 2: return launch_batched_cfg<MODE, 4, 13, false>(pl, st);
-        case 3: return launch_batched_cfg<MODE, 4, 7, false>(pl, st);
-        case 4: return launch_batched_cfg<MODE, 8, 7, true>(pl, st);
-        default: return launch_batched_cfg<MODE, 4, 13, true>(pl, st);
+        case 0: return launch_batched_cfg<MODE, 8, 13, false, 1>(pl, st);
+        case 1: return launch_batched_cfg<MODE, 8, 7, false, 1>(pl, st);
+        case 2: return launch_batched_cfg<MODE, 4, 13, false, 1>(pl, st);
+        case 3: return launch_batched_cfg<MODE, 4, 7, false, 1>(pl, st);
+        case 4: return launch_batched_cfg<MODE, 8, 7, true, 1>(pl, st);
+        case 5: return launch_batched_cfg<MODE, 4, 13, true, 1>(pl, st);
+        default:
+            if constexpr (MODE == MODE_F64) {
+                set_error("tile configuration %d is for float32 and bf16 only", cfg);
+                return NEGF_EINVAL;
+            } else {
+                if (cfg == 6) return launch_batched_cfg<MODE, 4, 7, false, 2>(pl, st);
+                return launch_batched_cfg<MODE, 4, 4, false, 2>(pl, st);
+            }
     }
 }
 
-int cfg_rows(int cfg) { return (cfg == 0 || cfg == 1 || cfg == 4) ? 8 : 4; }
+// rows i per workgroup of a configuration
+int cfg_rows(int cfg) { return (cfg == 0 || cfg == 1 || cfg == 4 || cfg >= 6) ? 8 : 4; }
 
 std::string batch_key(int mode, const std::vector<int>& n) {
     std::string k = "s2bB_" + std::to_string(mode);

@@ -103,12 +103,14 @@ def generate(seeds, tol=1e-4, dtype="bf16", chunk=16, log=print, save_path=None)
             G0 = negf.g0_build(ctx, hfs, tau, s.beta)
             ii, jj, qq = sample_points(sub[k], mats[k][0], s.n_tau)
             di = lambda a: torch.from_numpy(a).cuda()
+            x_d = torch.from_numpy(np.ascontiguousarray(mats[k][0])).cuda()
+            tau_d = torch.from_numpy(tau).cuda()
             if r.status != negf.OK:
                 # excluded from training (NaN row): the plain SCF did not converge for it
                 out[c0 + k] = np.nan
                 log(f"generate: system {sub[k]} stopped with status {r.status} after {r.iters} steps")
             else:
-                t = negf.mlp_targets(ctx, r.G, G0, 1.0, di(ii), di(jj), di(qq))
+                t = negf.mlp_targets(ctx, s, x_d, tau_d, r.G, G0, 1.0, di(ii), di(jj), di(qq))
                 out[c0 + k] = t.cpu().numpy()
                 iters.append(r.iters)
             del G0
@@ -118,6 +120,27 @@ def generate(seeds, tol=1e-4, dtype="bf16", chunk=16, log=print, save_path=None)
         if save_path:
             np.save(save_path, out[:c0 + len(sub)])
     ctx.close()
+    return out
+
+
+def convert_raw(seeds, raw, log=print):
+    """Targets stored as plain dG (out_scale 1, no envelope) -> dG / e at the same
+    sample points (e from negf_mlp_envelope); NaN rows stay NaN."""
+    torch, negf, W = _imports()
+    ctx = negf.Context(0)
+    out = np.array(raw, dtype=np.float32, copy=True)
+    base = W.config_sigma_bench()
+    for k, seed in enumerate(seeds):
+        if not np.all(np.isfinite(out[k])):
+            continue
+        s = W.random_potential_system(seed, base)
+        x, x_d, v_d, tau_d, _ = _dev_setup(torch, negf, s)
+        ii, jj, qq = sample_points(seed, x, s.n_tau)
+        di = lambda a: torch.from_numpy(a).cuda()
+        e = negf.mlp_envelope(ctx, s, x_d, tau_d, di(ii), di(jj), di(qq)).cpu().numpy()
+        out[k] = out[k] / e
+    ctx.close()
+    log(f"convert: {len(seeds)} systems")
     return out
 
 
@@ -277,7 +300,7 @@ def summarize(rows):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["generate", "train", "evaluate"])
+    ap.add_argument("cmd", choices=["generate", "convert", "train", "evaluate"])
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--count", type=int, default=len(TRAIN_SEEDS))
     ap.add_argument("--data", default=None, help="targets file (.npy): written by generate, read by train")
@@ -290,6 +313,10 @@ def main():
         seeds = list(TRAIN_SEEDS)[args.first:args.first + args.count]
         t = generate(seeds, log=log, save_path=args.data)
         np.save(args.data, t)
+    elif args.cmd == "convert":
+        raw = np.load(args.data, allow_pickle=False)
+        seeds = list(TRAIN_SEEDS)[args.first:args.first + raw.shape[0]]
+        np.save(args.out, convert_raw(seeds, raw, log=log))
     elif args.cmd == "train":
         parts = [np.load(p, allow_pickle=False) for p in args.data.split(",")]
         t = np.concatenate(parts)

@@ -86,6 +86,7 @@ def test_guess_matches_oracle(env):
     ii = np.tile(iu[0], s.n_tau)
     jj = np.tile(iu[1], s.n_tau)
     y, _ = mlp.forward(p, mlp.features(st.x, st.v, s.centres, s.charges, st.tau, s.beta, ii, jj, qq))
+    y = y * mlp.envelope(st.x, s.centres, st.tau, s.beta, ii, jj, qq)
     ref = G0.copy()
     dG = np.zeros_like(G0)
     dG[qq, ii, jj] = y * scale
@@ -97,3 +98,25 @@ def test_guess_matches_oracle(env):
     o = out.cpu().numpy()
     assert np.max(np.abs(o - ref)) < 1e-6 * scale * 10 + 1e-12
     assert np.array_equal(o, o.transpose(0, 2, 1))
+
+
+def test_targets_and_envelope_match_oracle(env):
+    """Training targets (G - G0) / (scale e) and the envelope at seeded samples."""
+    torch, ctx = env
+    s = _sys()
+    st = fedvr.Setup(s)
+    rng = np.random.default_rng(3)
+    G = W.random_symmetric_slices(s.n_b, s.n_tau, 21)
+    G0 = W.random_symmetric_slices(s.n_b, s.n_tau, 22)
+    S = 777
+    ii = rng.integers(0, s.n_b, S).astype(np.int32)
+    jj = rng.integers(0, s.n_b, S).astype(np.int32)
+    qq = rng.integers(0, s.n_tau, S).astype(np.int32)
+    e_ref = mlp.envelope(st.x, s.centres, st.tau, s.beta, ii, jj, qq)
+    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    di = lambda a: torch.from_numpy(a).cuda()
+    e = negf.mlp_envelope(ctx, s, d64(st.x), d64(st.tau), di(ii), di(jj), di(qq)).cpu().numpy()
+    assert np.max(np.abs(e - e_ref) / e_ref) < 1e-6
+    t = negf.mlp_targets(ctx, s, d64(st.x), d64(st.tau), d64(G), d64(G0), 0.5, di(ii), di(jj), di(qq))
+    t_ref = (G[qq, ii, jj] - G0[qq, ii, jj]) / (0.5 * e_ref)
+    assert np.max(np.abs(t.cpu().numpy() - t_ref)) < 1e-6 * np.max(np.abs(t_ref))

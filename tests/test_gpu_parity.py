@@ -61,12 +61,17 @@ def test_sigma2b_f64(ctx, torch_mod, n, n_tau):
     assert relerr(host(out), ref) < TOL64
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", range(8))
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_sigma2b_every_tile_config(ctx, torch_mod, cfg, dtype):
     """Every tile configuration the tuner can pick, on a size with several column
     chunks (n > 208) and on a ragged small size."""
-    for n, n_tau in ((221, 3), (37, 5)):
+    if dtype == "f64" and cfg >= 6:
+        with pytest.raises(negf.NegfError):
+            negf.sigma2b_set_config(ctx, 37, dtype, cfg)
+            negf.sigma2b(ctx, dev(torch_mod, _pos_V(37, 11)), dev(torch_mod, W.random_symmetric_slices(37, 5, 12)), 2)
+        return
+    for n, n_tau in ((221, 3), (37, 5), (9, 4)):
         V = _pos_V(n, 11)
         G = W.random_symmetric_slices(n, n_tau, 12)
         ref = S.sigma2b(V, G, 2)
@@ -86,7 +91,7 @@ def test_sigma2b_tuner(ctx, torch_mod):
     V = _pos_V(n, 13)
     G = W.random_symmetric_slices(n, n_tau, 14)
     best, ms = negf.sigma2b_tune(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
-    assert 0 <= best < 6 and ms[best] > 0 and all(m > 0 for m in ms)
+    assert 0 <= best < 6 and ms[best] > 0 and all(m > 0 for m in ms[:6]) and all(m == -1.0 for m in ms[6:])
     out = negf.sigma2b(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
     assert relerr(host(out), S.sigma2b(V, G, 2)) < TOL64
 
