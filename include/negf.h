@@ -348,8 +348,8 @@ int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* systems,
  * the fallback.) Features of a sample (i, j, tau): x_i/10, x_j/10, v(x_i), v(x_j),
  * Chebyshev T_0..T_15(2 tau/beta - 1), Z_1..Z_3, X_1/10..X_3/10 (nuclei zero-padded):
  * 26 numbers. Network 26 -> 256 -> 256 -> 256 -> 1, tanh on the hidden layers; its
- * output is multiplied by a fixed envelope (negf_mlp_envelope) that confines the
- * correction to the neighbourhood of the nuclei and of tau = 0 and beta;
+ * output is multiplied by a fixed envelope (negf_mlp_envelope) that follows the
+ * decay of the correction away from the nuclei;
  * parameters are one float32 array in the order W1 (26 x 256, row-major, input-major),
  * b1, W2 (256 x 256), b2, W3, b3, W4 (256 x 1), b4. */
 int negf_mlp_param_count(int* count);
@@ -362,8 +362,9 @@ int negf_mlp_features(negf_ctx* ctx, int n_b, const double* x, const double* v, 
                       int n_samples, const int* ii, const int* jj, const int* qq, float* F, void* stream);
 
 /* Envelope of the learned correction at the samples (dev, float32):
- * e(i, j, tau) = exp(-(d_i + d_j)/5 - min(tau, beta - tau)/10), d_i = distance of
- * node x_i to the nearest of the n_c nuclei Xc (host; n_c = 0: d = 0). x, tau dev. */
+ * e(i, j) = (1 + (d_i + d_j)/5)^(-3/2), d_i = distance of node x_i to the nearest of
+ * the n_c nuclei Xc (host; n_c = 0: d = 0); tau and beta are accepted for the
+ * signature's sake and do not enter. x, tau dev. */
 int negf_mlp_envelope(negf_ctx* ctx, const double* x, int n_c, const double* Xc, const double* tau,
                       double beta, int n_samples, const int* ii, const int* jj, const int* qq,
                       float* env, void* stream);

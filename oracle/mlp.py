@@ -72,20 +72,19 @@ def features(x, v, centres, charges, tau, beta, ii, jj, qq):
     return F
 
 
-ENV_LX = 5.0
-ENV_LT = 10.0
+ENV_L = 5.0
 
 
 def envelope(x, centres, tau, beta, ii, jj, qq):
     """Fixed envelope of the learned correction at the samples:
-    exp(-(d_i + d_j)/L_X - min(tau, beta - tau)/L_T), d_i the distance of node i to
-    the nearest nucleus (0 without nuclei). A design choice of the learned guess,
-    not part of the paper's method."""
+    (1 + (d_i + d_j)/L)^(-3/2), d_i the distance of node i to the nearest nucleus
+    (0 without nuclei), L = 5; independent of tau. A design choice of the learned
+    guess, not part of the paper's method."""
     x = np.asarray(x, dtype=np.float64)
     c = np.asarray(centres, dtype=np.float64).reshape(-1)
     d = np.min(np.abs(x[:, None] - c[None, :]), axis=1) if c.size else np.zeros_like(x)
-    t = np.asarray(tau, dtype=np.float64)[np.asarray(qq)]
-    return np.exp(-(d[np.asarray(ii)] + d[np.asarray(jj)]) / ENV_LX - np.minimum(t, beta - t) / ENV_LT)
+    u = 1.0 + (d[np.asarray(ii)] + d[np.asarray(jj)]) / ENV_L
+    return u ** -1.5
 
 
 def forward(p, X):

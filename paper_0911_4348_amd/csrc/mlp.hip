@@ -1,11 +1,11 @@
 // Learned initial guess: a tau-resolved 4-layer MLP (float32) that predicts
 // dG_ij(tau) = G(tau) - G0(tau) from per-sample features; the guess is
 // G_init = G0 + (dG + dG^T)/2. Training and inference run in these kernels.
-// The network output y is scaled by a fixed envelope that localises the
-// correction where correlation lives, near the nuclei and near the ends of
-// [0, beta]: dG = s e(i, j, tau) y with
-//   e = exp(-(d_i + d_j)/L_X - min(tau, beta - tau)/L_T),
-// d_i the distance of node i to the nearest nucleus, L_X = 5, L_T = 10 (a.u.).
+// The network output y is scaled by a fixed envelope that follows the decay of
+// the correction away from the nuclei: dG = s e(i, j) y with
+//   e = (1 + (d_i + d_j)/L)^(-3/2),
+// d_i the distance of node i to the nearest nucleus, L = 5 a.u.; the network's
+// residual error far from the nuclei is damped by the same factor.
 //
 // Features per sample (i, j, tau): x_i/s, x_j/s, v_i, v_j, T_0..T_15(2 tau/beta - 1),
 // Z_1..Z_3, X_1/s..X_3/s (s = 10, nuclei zero-padded). Network 26 -> 256 -> 256 ->
@@ -34,7 +34,7 @@ inline unsigned grid_for(long total) {
     return (unsigned)b;
 }
 
-constexpr double ENV_LX = 5.0, ENV_LT = 10.0;
+constexpr double ENV_L = 5.0;
 
 struct NucTab {
     float Z[N_CENT];
@@ -51,7 +51,10 @@ __device__ __forceinline__ double envelope(double xi, double xj, double tau, dou
             dj = fmin(dj, fabs(xj - (double)nt.X[c]));
         }
     }
-    return exp(-(di + dj) / ENV_LX - fmin(tau, beta - tau) / ENV_LT);
+    (void)tau;
+    (void)beta;
+    const double u = 1.0 + (di + dj) / ENV_L;
+    return 1.0 / (u * sqrt(u));
 }
 
 __device__ __forceinline__ void feature_row(float* f, float xi, float xj, float vi, float vj, float t,

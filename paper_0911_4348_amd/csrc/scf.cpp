@@ -36,6 +36,20 @@ namespace {
 
 enum { PH_LOW = 0, PH_F64 = 1, PH_DONE = 2 };
 
+// out[0] = trace of the n x n matrix A
+__global__ __launch_bounds__(256) void k_trace(int n, const double* __restrict__ A, double* out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += A[(long)i * n + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 struct Sys {
     int b;                   // index in the caller's arrays
     int n;
@@ -55,6 +69,9 @@ struct Sys {
     bool conv = false;
     bool nan = false;
     bool hf_ok = true;       // HF converged; otherwise the system is not iterated
+    bool learned = false;    // started from the learned guess
+    bool restarted = false;  // learned start abandoned for G0 after a non-finite energy
+    int wasted = 0;          // steps spent before such a restart
     int log_n = 0;
 };
 
@@ -270,15 +287,28 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
     }
 
     // ---------------- starting G
+    double* dtr;
+    NEGF_TRY(scratch_t(ctx, "scf_trace", 1, &dtr));
     for (Sys& y : S) {
         const negf_system_t& s = systems[y.b];
         if (G_guess && G_guess[y.b]) {
             HIP_TRY(hipMemcpyAsync(y.G, G_guess[y.b], sizeof(double) * y.nn * n_tau, hipMemcpyDeviceToDevice, st));
         } else {
             NEGF_TRY(g0_build<double>(ctx, y.n, n_tau, tau.data(), s.beta, y.eps, y.C, y.mu, y.G, st));
-            if (o->guess_params)
+            if (o->guess_params) {
                 NEGF_TRY(negf_mlp_guess(ctx, o->guess_params, o->guess_scale, y.n, y.x, y.v, s.pot.n_c, s.pot.X,
                                         s.pot.Z, n_tau, (const double*)dtau, s.beta, y.G, y.G, st));
+                // the learned start must hold the right number of electrons,
+                // N = -sigma Tr G(beta^-), to within 2%; otherwise start from G0
+                hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, y.n, y.G + (long)(n_tau - 1) * y.nn, dtr);
+                LAUNCH_CHECK();
+                double tr = 0.0;
+                HIP_TRY(hipMemcpyAsync(&tr, dtr, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                const double N = -s.sigma * tr;
+                if (std::isfinite(N) && std::fabs(N - s.n_elec) <= 0.02 * s.n_elec) y.learned = true;
+                else NEGF_TRY(g0_build<double>(ctx, y.n, n_tau, tau.data(), s.beta, y.eps, y.C, y.mu, y.G, st));
+            }
         }
         if (low) {
             NEGF_TRY(to_f32(y.G, y.Gf, y.nn * n_tau, st));
@@ -397,7 +427,20 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             const double E = hEN[2 * r] + systems[y.b].e_nn, N = hEN[2 * r + 1];
             y.E = E;
             y.N = N;
-            const int step = (y.phase == PH_F64 ? y.steps_low : 0) + y.k;
+            const int step = y.wasted + (y.phase == PH_F64 ? y.steps_low : 0) + y.k;
+            if ((!std::isfinite(E) || !std::isfinite(N)) && y.learned && !y.restarted) {
+                // the learned start left the basin of the iteration: restart from G0
+                y.wasted = step + 1;
+                y.restarted = true;
+                NEGF_TRY(g0_build<double>(ctx, y.n, n_tau, tau.data(), systems[y.b].beta, y.eps, y.C, y.mu, y.G, st));
+                if (low) NEGF_TRY(to_f32(y.G, y.Gf, y.nn * n_tau, st));
+                y.phase = low ? PH_LOW : PH_F64;
+                y.k = 0;
+                y.steps_low = 0;
+                y.E_prev = NAN;
+                y.limit = fixed ? o->fixed_iters : o->max_iter;
+                continue;
+            }
             if (!std::isfinite(E) || !std::isfinite(N)) {
                 // this system stops; the others go on
                 set_error("energy or particle number not finite at step %d (system %d)", step, y.b);
@@ -468,7 +511,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
     for (const Sys& y : S) {
         if (E_out) E_out[y.b] = y.E;
         if (N_out) N_out[y.b] = y.N;
-        if (iters) iters[y.b] = y.steps_low + y.k;
+        if (iters) iters[y.b] = y.wasted + y.steps_low + y.k;
         if (log_n) log_n[y.b] = y.log_n;
         if (status)
             status[y.b] = y.nan ? NEGF_ENAN : ((!y.hf_ok || (!fixed && !y.conv)) ? NEGF_ENOCONV : NEGF_OK);

@@ -65,21 +65,18 @@ def test_training_reduces_loss():
 
 
 def test_envelope_properties():
-    """1 at a nucleus at tau = 0 and beta; symmetric in (i, j) and tau -> beta - tau;
-    the product of independent exponential factors."""
+    """1 at a nucleus; symmetric in (i, j); independent of tau; (1 + D/5)^(-3/2)."""
     x = np.linspace(-10, 10, 41)
     tau = np.linspace(0.0, 20.0, 11)
     c = np.array([-2.0, 3.0])
     ii, jj, qq = np.meshgrid(np.arange(41), np.arange(41), np.arange(11), indexing="ij")
     ii, jj, qq = ii.ravel(), jj.ravel(), qq.ravel()
     e = mlp.envelope(x, c, tau, 20.0, ii, jj, qq)
-    e_sw = mlp.envelope(x, c, tau, 20.0, jj, ii, 10 - qq)
-    assert np.allclose(e, e_sw, rtol=0, atol=1e-15)
+    assert np.array_equal(e, mlp.envelope(x, c, tau, 20.0, jj, ii, 10 - qq))
     k = int(np.argmin(np.abs(x - 3.0)))
-    assert mlp.envelope(x, c, tau, 20.0, [k], [k], [0])[0] == 1.0
-    assert mlp.envelope(x, c, tau, 20.0, [k], [k], [10])[0] == 1.0
-    # distance 5 from the nearest nucleus on both indices, tau = 10 from the end: e^-2 e^-1
+    assert mlp.envelope(x, c, tau, 20.0, [k], [k], [3])[0] == 1.0
+    # distance 5 from the nearest nucleus on both indices: (1 + 10/5)^(-3/2) = 3^(-3/2)
     m = int(np.argmin(np.abs(x - 8.0)))
-    assert np.isclose(mlp.envelope(x, c, tau, 20.0, [m], [m], [5])[0], np.exp(-2.0 - 1.0), rtol=1e-14)
+    assert np.isclose(mlp.envelope(x, c, tau, 20.0, [m], [m], [5])[0], 3.0 ** -1.5, rtol=1e-14)
     # no nuclei: distance 0
-    assert np.isclose(mlp.envelope(x, [], tau, 20.0, [0], [5], [0])[0], 1.0)
+    assert mlp.envelope(x, [], tau, 20.0, [0], [5], [0])[0] == 1.0
