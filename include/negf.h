@@ -287,10 +287,13 @@ typedef struct {
     double hf_tol;           /* HF stopping rule (<= 0: 1e-13) */
     int hf_max_iter;         /* (<= 0: 1000) */
     const float* guess_params;   /* dev, nullable: start from the learned guess of this
-                                    network (negf_mlp_guess on G0) instead of G0 */
+                                    network (negf_mlp_guess on G0, bf16 inference) instead
+                                    of G0; a guess whose electron count is off by more than
+                                    2%, or whose iteration turns non-finite, is replaced by G0 */
     double guess_scale;      /* its output scale */
     int tune;                /* 1: run the batch tile autotuner first (once per batch shape) */
     int no_graph;            /* 1: launch every iteration directly (no HIP graphs) */
+    int progress;            /* 1: one line per iteration on stderr (systems left, max |dE|, ms) */
 } negf_opts_t;
 
 typedef struct {
@@ -391,11 +394,15 @@ int negf_mlp_train_step(negf_ctx* ctx, float* params, float* m, float* v, int st
 
 /* Inference on the whole grid: for every q and i <= j, G_out[q][i][j] = G_out[q][j][i]
  * = (G0[q][i][j] + G0[q][j][i])/2 + out_scale e(i, j, tau_q) y(i, j, tau_q), e the
- * envelope of negf_mlp_envelope. x, v, tau (dev, float64);
+ * envelope of negf_mlp_envelope. dtype NEGF_F32: the network in float32 (as trained);
+ * NEGF_BF16: weights and activations rounded to bf16 on the matrix cores with float32
+ * accumulation (about 4x faster; output perturbed by ~1e-2 relative). x, v, tau
+ * (dev, float64);
  * G0, G_out (dev, float64 [n_tau][n_b][n_b]; may alias). */
 int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
                    const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,
-                   const double* tau, double beta, const double* G0, double* G_out, void* stream);
+                   const double* tau, double beta, const double* G0, double* G_out, int dtype,
+                   void* stream);
 
 #ifdef __cplusplus
 }

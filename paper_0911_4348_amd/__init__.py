@@ -61,7 +61,7 @@ class OptsT(C.Structure):
                 ("fixed_iters", C.c_int), ("dtype", C.c_int), ("conv_algo", C.c_int),
                 ("symmetrize", C.c_int), ("refine_tol", C.c_double), ("hf_tol", C.c_double),
                 ("hf_max_iter", C.c_int), ("guess_params", C.c_void_p), ("guess_scale", C.c_double),
-                ("tune", C.c_int), ("no_graph", C.c_int)]
+                ("tune", C.c_int), ("no_graph", C.c_int), ("progress", C.c_int)]
 
 
 class IterLogT(C.Structure):
@@ -115,7 +115,7 @@ _SIGS = {
     "negf_mlp_train_step": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, C.c_double, C.c_int, _VP, _VP, _VP, _DP,
                                       _VP]),
     "negf_mlp_guess": (C.c_int, [_VP, _VP, C.c_double, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP,
-                                 C.c_double, _VP, _VP, _VP]),
+                                 C.c_double, _VP, _VP, C.c_int, _VP]),
 }
 
 
@@ -403,10 +403,10 @@ def system_struct(sysd):
 
 
 def _opts(alpha, tol, max_iter, fixed_iters, dtype, conv, symmetrize, refine_tol, guess=None, guess_scale=1.0,
-          tune=False, graphs=True):
+          tune=False, graphs=True, progress=False):
     return OptsT(float(alpha), float(tol), int(max_iter), int(fixed_iters), _DT[dtype], int(conv),
                  int(symmetrize), float(refine_tol), 0.0, 0, _dev_ptr(guess), float(guess_scale), int(tune),
-                 0 if graphs else 1)
+                 0 if graphs else 1, int(progress))
 
 
 def _records(logs, base, count):
@@ -416,19 +416,21 @@ def _records(logs, base, count):
 
 def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
         conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
-        allow_noconv=False, guess=None, guess_scale=1.0, graphs=True, stream=None) -> SCFOut:
+        allow_noconv=False, guess=None, guess_scale=1.0, graphs=True, tune=False, progress=False,
+        stream=None) -> SCFOut:
     """negf_scf for a workloads.System (guess: learned-guess parameters on the device)."""
     out = scf_batched(ctx, [sysd], alpha=alpha, tol=tol, max_iter=max_iter, fixed_iters=fixed_iters, dtype=dtype,
                       conv=conv, symmetrize=symmetrize, refine_tol=refine_tol,
                       G_guess=None if G_guess is None else [G_guess], want_G=want_G, allow_noconv=allow_noconv,
-                      guess=guess, guess_scale=guess_scale, graphs=graphs, single=True, stream=stream)
+                      guess=guess, guess_scale=guess_scale, graphs=graphs, tune=tune, single=True,
+                      progress=progress, stream=stream)
     return out[0]
 
 
 def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
                 conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
                 allow_noconv=False, guess=None, guess_scale=1.0, tune=False, graphs=True, single=False,
-                stream=None):
+                progress=False, stream=None):
     """negf_scf_batched (single=True: negf_scf) for a list of workloads.System; returns a list of SCFOut."""
     torch = _torch()
     B = len(systems)
@@ -438,7 +440,7 @@ def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed
         structs[b] = st_
         keep.append(k)
     o = _opts(alpha, tol, max_iter, fixed_iters, dtype, conv, symmetrize, refine_tol, guess, guess_scale, tune,
-              graphs)
+              graphs, progress)
     Gs = [torch.empty((sd.n_tau, sd.n_b, sd.n_b), dtype=torch.float64, device="cuda") if want_G else None
           for sd in systems]
     Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
@@ -570,12 +572,12 @@ def mlp_train_step(ctx: Context, params, m, v, step, lr, F, target, grad_out=Non
     return loss.value if want_loss else None
 
 
-def mlp_guess(ctx: Context, params, out_scale, sysd, x_d, v_d, tau_d, G0, G_out=None, stream=None):
+def mlp_guess(ctx: Context, params, out_scale, sysd, x_d, v_d, tau_d, G0, G_out=None, dtype="f32", stream=None):
     torch = _torch()
     n_c, X, Z = _nuclei(sysd)
     if G_out is None:
         G_out = torch.empty_like(G0)
     _check(lib().negf_mlp_guess(ctx.handle, _dev_ptr(params), float(out_scale), sysd.n_b, _dev_ptr(x_d),
                                 _dev_ptr(v_d), n_c, _dptr(X), _dptr(Z), tau_d.shape[0], _dev_ptr(tau_d),
-                                float(sysd.beta), _dev_ptr(G0), _dev_ptr(G_out), _stream(stream)))
+                                float(sysd.beta), _dev_ptr(G0), _dev_ptr(G_out), _DT[dtype], _stream(stream)))
     return G_out

@@ -315,6 +315,83 @@ NucTab make_nuc(int n_c, const double* X, const double* Z) {
     return t;
 }
 
+// ---------------------------------------------------------------- bf16 inference
+// Inference-only path on the bf16 matrix cores (float32 accumulation): weights
+// transposed to [N][K] bf16 once per call, activations kept in bf16 between
+// layers, bias and tanh fused. Layer 1's K = 26 is zero-padded to 32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int K1P = 32;
+
+// WtT[n][k] = bf16(W[k][n]) for k < K (zero for K <= k < KP)
+__global__ void k_weights_bf16(int K, int KP, int N, const float* __restrict__ W, __bf16* __restrict__ WtT) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)N * KP; e += (long)gridDim.x * blockDim.x) {
+        const int n = (int)(e / KP), k = (int)(e % KP);
+        WtT[e] = (__bf16)(k < K ? W[(long)k * N + n] : 0.f);
+    }
+}
+
+// Features of a grid range (as k_features_grid) in bf16, rows padded to K1P.
+__global__ void k_features_grid_bf16(int n, long g0, long S, const double* __restrict__ x,
+                                     const double* __restrict__ v, const double* __restrict__ tau, double beta,
+                                     NucTab nt, __bf16* __restrict__ F) {
+    const long P = (long)n * (n + 1) / 2;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < S; s += (long)gridDim.x * blockDim.x) {
+        const long g = g0 + s;
+        const int q = (int)(g / P);
+        int i, j;
+        pair_of(n, g % P, &i, &j);
+        float f[D_IN];
+        feature_row(f, (float)x[i], (float)x[j], (float)v[i], (float)v[j], (float)(2.0 * tau[q] / beta - 1.0), nt);
+        __bf16* o = F + s * K1P;
+        for (int k = 0; k < K1P; ++k) o[k] = (__bf16)(k < D_IN ? f[k] : 0.f);
+    }
+}
+
+// C[S][HID] = tanh(A[S][K] W + b): block = 4 waves x 16 rows, each wave all HID
+// columns (16 tiles of 16); A rows and WtT rows are read as 16-byte fragments.
+__global__ __launch_bounds__(256) void k_dense_bf16(int S, int K, const __bf16* __restrict__ A,
+                                                    const __bf16* __restrict__ WtT, const float* __restrict__ b,
+                                                    __bf16* __restrict__ C) {
+    constexpr int NT = HID / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lc = lane & 15, lg = lane >> 4;
+    const long r0 = (long)blockIdx.x * 64 + w * 16;
+    fv4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = fv4{0.f, 0.f, 0.f, 0.f};
+    const long ra = r0 + lc;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a;
+        if (ra < S) a = *reinterpret_cast<const bf16x8*>(A + ra * K + k0 + lg * 8);
+        else
+            for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8 bb = *reinterpret_cast<const bf16x8*>(WtT + (long)(t * 16 + lc) * K + k0 + lg * 8);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long row = r0 + 4 * lg + r;
+            const int col = t * 16 + lc;
+            if (row < S) C[row * HID + col] = (__bf16)tanhf(acc[t][r] + b[col]);
+        }
+}
+
+__global__ void k_out_bf16(int S, const __bf16* __restrict__ a3, const float* __restrict__ W4,
+                           const float* __restrict__ b4, float* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    for (long s = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6; s < S; s += ((long)gridDim.x * blockDim.x) >> 6) {
+        float acc = 0.f;
+        for (int k = lane; k < HID; k += 64) acc += (float)a3[s * HID + k] * W4[k];
+        acc = wave_sum(acc);
+        if (lane == 0) y[s] = acc + b4[0];
+    }
+}
+
 int forward(negf_ctx* ctx, int S, const float* F, const float* p, float** a1, float** a2, float** a3, float* y,
             hipStream_t st) {
     NEGF_TRY(scratch_t(ctx, "mlp_a1", (size_t)S * HID, a1));
@@ -488,19 +565,60 @@ extern "C" int negf_mlp_train_step(negf_ctx* ctx, float* params, float* m, float
 
 extern "C" int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
                               const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,
-                              const double* tau, double beta, const double* G0, double* G_out, void* stream) {
+                              const double* tau, double beta, const double* G0, double* G_out, int dtype,
+                              void* stream) {
     NEGF_REQUIRE(ctx && params && x && v && tau && G0 && G_out, "NULL argument");
     NEGF_REQUIRE(n_b >= 1 && n_tau >= 2 && beta > 0 && out_scale > 0, "bad sizes");
     NEGF_REQUIRE(n_c >= 0 && n_c <= N_CENT && (n_c == 0 || (Xc && Zc)), "n_c must be 0..3");
+    NEGF_REQUIRE(dtype == NEGF_F32 || dtype == NEGF_BF16, "dtype must be NEGF_F32 or NEGF_BF16");
     NEGF_TRY(bind_device(ctx));
     hipStream_t st = (hipStream_t)stream;
     const long P = (long)n_b * (n_b + 1) / 2;
     const long total = P * n_tau;
     const long CH = 1L << 20;
-    float *F, *y;
-    NEGF_TRY(scratch_t(ctx, "mlp_F", (size_t)CH * D_IN, &F));
+    float* y;
     NEGF_TRY(scratch_t(ctx, "mlp_yg", (size_t)CH, &y));
     const NucTab nt = make_nuc(n_c, Xc, Zc);
+    if (dtype == NEGF_BF16) {
+        __bf16 *W1, *W2, *W3, *Fb, *h1, *h2;
+        NEGF_TRY(scratch_t(ctx, "mlpb_W1", (size_t)HID * K1P, &W1));
+        NEGF_TRY(scratch_t(ctx, "mlpb_W2", (size_t)HID * HID, &W2));
+        NEGF_TRY(scratch_t(ctx, "mlpb_W3", (size_t)HID * HID, &W3));
+        NEGF_TRY(scratch_t(ctx, "mlpb_F", (size_t)CH * K1P, &Fb));
+        NEGF_TRY(scratch_t(ctx, "mlpb_h1", (size_t)CH * HID, &h1));
+        NEGF_TRY(scratch_t(ctx, "mlpb_h2", (size_t)CH * HID, &h2));
+        hipLaunchKernelGGL(k_weights_bf16, dim3(grid_for((long)HID * K1P)), dim3(256), 0, st, D_IN, K1P, HID,
+                           params + OFF_W1, W1);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_weights_bf16, dim3(grid_for((long)HID * HID)), dim3(256), 0, st, HID, HID, HID,
+                           params + OFF_W2, W2);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_weights_bf16, dim3(grid_for((long)HID * HID)), dim3(256), 0, st, HID, HID, HID,
+                           params + OFF_W3, W3);
+        LAUNCH_CHECK();
+        for (long g0 = 0; g0 < total; g0 += CH) {
+            const long S = total - g0 < CH ? total - g0 : CH;
+            const unsigned nb = (unsigned)((S + 63) / 64);
+            hipLaunchKernelGGL(k_features_grid_bf16, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, x, v, tau,
+                               beta, nt, Fb);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_dense_bf16, dim3(nb), dim3(256), 0, st, (int)S, K1P, Fb, W1, params + OFF_B1, h1);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_dense_bf16, dim3(nb), dim3(256), 0, st, (int)S, HID, h1, W2, params + OFF_B2, h2);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_dense_bf16, dim3(nb), dim3(256), 0, st, (int)S, HID, h2, W3, params + OFF_B3, h1);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_out_bf16, dim3(grid_for(S * 64)), dim3(256), 0, st, (int)S, h1, params + OFF_W4,
+                               params + OFF_B4, y);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_scatter_guess, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, y, out_scale, x, tau,
+                               beta, nt, G0, G_out);
+            LAUNCH_CHECK();
+        }
+        return NEGF_OK;
+    }
+    float* F;
+    NEGF_TRY(scratch_t(ctx, "mlp_F", (size_t)CH * D_IN, &F));
     for (long g0 = 0; g0 < total; g0 += CH) {
         const long S = total - g0 < CH ? total - g0 : CH;
         hipLaunchKernelGGL(k_features_grid, dim3(grid_for(S)), dim3(256), 0, st, n_b, g0, S, x, v, tau, beta, nt, F);

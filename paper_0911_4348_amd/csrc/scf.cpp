@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -30,7 +31,8 @@ using namespace negf;
 
 extern "C" int negf_mlp_guess(negf_ctx* ctx, const float* params, double out_scale, int n_b, const double* x,
                               const double* v, int n_c, const double* Xc, const double* Zc, int n_tau,
-                              const double* tau, double beta, const double* G0, double* G_out, void* stream);
+                              const double* tau, double beta, const double* G0, double* G_out, int dtype,
+                              void* stream);
 
 namespace {
 
@@ -297,7 +299,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             NEGF_TRY(g0_build<double>(ctx, y.n, n_tau, tau.data(), s.beta, y.eps, y.C, y.mu, y.G, st));
             if (o->guess_params) {
                 NEGF_TRY(negf_mlp_guess(ctx, o->guess_params, o->guess_scale, y.n, y.x, y.v, s.pot.n_c, s.pot.X,
-                                        s.pot.Z, n_tau, (const double*)dtau, s.beta, y.G, y.G, st));
+                                        s.pot.Z, n_tau, (const double*)dtau, s.beta, y.G, y.G, NEGF_BF16, st));
                 // the learned start must hold the right number of electrons,
                 // N = -sigma Tr G(beta^-), to within 2%; otherwise start from G0
                 hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, y.n, y.G + (long)(n_tau - 1) * y.nn, dtr);
@@ -421,6 +423,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
 
         // stopping rule per system
         std::vector<int> dy_lo, dy_hi;
+        double max_dE = 0.0;
         for (int r = 0; r < batch; ++r) {
             Sys& y = S[r];
             if (y.phase == PH_DONE) continue;
@@ -450,6 +453,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
                 continue;
             }
             const double dE = std::isnan(y.E_prev) ? NAN : E - y.E_prev;
+            if (std::isfinite(dE)) max_dE = std::max(max_dE, std::fabs(dE));
             // a fixed-count run ignores the tolerance; the float64 refinement of
             // the mixed form has its own
             const double tol = (low && y.phase == PH_F64 && o->refine_tol > 0) ? o->refine_tol : o->tol;
@@ -483,6 +487,11 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             } else {
                 y.phase = PH_DONE;
             }
+        }
+        if (o->progress) {
+            std::fprintf(stderr, "negf_scf: iteration done in %.0f ms, %d of %d systems going on, max |dE| %.2e\n", ms,
+                         (int)(dy_lo.size() + dy_hi.size()), batch, max_dE);
+            std::fflush(stderr);
         }
         // (b) Dyson step of every system that goes on
         if (!dy_lo.empty() || !dy_hi.empty()) {

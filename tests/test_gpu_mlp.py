@@ -98,6 +98,12 @@ def test_guess_matches_oracle(env):
     o = out.cpu().numpy()
     assert np.max(np.abs(o - ref)) < 1e-6 * scale * 10 + 1e-12
     assert np.array_equal(o, o.transpose(0, 2, 1))
+    # bf16 inference on the matrix cores: the correction within a few percent of its size
+    ob = negf.mlp_guess(ctx, torch.from_numpy(p.astype(np.float32)).cuda(), scale, s, d64(st.x), d64(st.v),
+                        d64(st.tau), d64(G0), dtype="bf16").cpu().numpy()
+    corr = ref - 0.5 * (G0 + G0.transpose(0, 2, 1))
+    assert np.max(np.abs(ob - ref)) < 3e-2 * np.max(np.abs(corr))
+    assert np.array_equal(ob, ob.transpose(0, 2, 1))
 
 
 def test_targets_and_envelope_match_oracle(env):
