@@ -320,7 +320,8 @@ def main():
         "sigma2b_ms": round(sig_avg, 3),
         "sigma2b_tuner": {"configs": ["8i x 208col", "8i x 112col", "4i x 208col", "4i x 112col",
                                       "8i x 112col 2-stage", "4i x 208col 2-stage", "4w x 2i x 112col",
-                                      "4w x 2i x 64col"],
+                                      "4w x 2i x 64col", "f64 VALU 8i x 40x40", "f64 VALU 4w x 2i x 40x40",
+                                      "f64 VALU 4w x 2i x 32x32"],
                           "ms": [round(m, 3) for m in tune_ms], "chosen": best},
         "dyson_ms": round(float(np.mean(dy_ms)), 3),
         "sigma2b_hbm_GBps": round(sigma2b_bytes(n, n_tau, elem) / (sig_avg * 1e-3) / 1e9, 1),

@@ -178,7 +178,7 @@ int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
  * per workgroup x column-chunk width) on the given input and stores the fastest
  * for (dtype, n_b) in the context; later negf_sigma2b calls with that dtype and
  * n_b use it. Arguments as for negf_sigma2b (Sigma_c is overwritten). *best
- * (host, nullable) receives the chosen index, ms (host, nullable, 8 entries) the
+ * (host, nullable) receives the chosen index, ms (host, nullable, 11 entries) the
  * measured times (-1 for a configuration that does not fit or does not exist
  * for this dtype). Synchronises. */
 int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
@@ -188,7 +188,9 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
  * 0..3 = (8 or 4 values of i per workgroup) x (208- or 112-column chunks) with
  * single-buffered k-panels; 4, 5 = 8 x 112 and 4 x 208 with double-buffered
  * k-panels; 6, 7 (NEGF_F32 and NEGF_BF16 only) = 4 waves with two values of i
- * each x 112- or 64-column chunks. */
+ * each x 112- or 64-column chunks; 8, 9, 10 (NEGF_F64 only) = float64 vector-ALU
+ * tiles: 8 waves x 40 x 40 blocks of M^(i), 4 waves with two values of i each x
+ * 40 x 40 or 32 x 32 blocks. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
 /* Sigma-2B (as negf_sigma2b) for `batch` systems of any sizes n_b[b] on one
@@ -206,14 +208,14 @@ int negf_sigma2b_batched(negf_ctx* ctx, int batch, const int* n_b, int n_tau, co
                          const void* const* V, const void* const* G, void* const* Sigma_c,
                          int dtype, void* stream);
 
-/* Pin the negf_sigma2b_batched tile configuration (0..7, as negf_sigma2b_set_config)
+/* Pin the negf_sigma2b_batched tile configuration (0..10, as negf_sigma2b_set_config)
  * for this dtype and multiset of n_b (host, batch ints). */
 int negf_sigma2b_batched_set_config(negf_ctx* ctx, int batch, const int* n_b, int dtype, int cfg);
 
 /* Autotuner for negf_sigma2b_batched: times each tile configuration on the
  * first pair_lim slice pairs of every system (0: all pairs), keeps the fastest
  * for this dtype and multiset of n_b. Sigma_c is overwritten (partly). *best,
- * ms[8] (host, nullable) as for negf_sigma2b_tune. Synchronises. */
+ * ms[11] (host, nullable) as for negf_sigma2b_tune. Synchronises. */
 int negf_sigma2b_batched_tune(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
                               const void* const* V, const void* const* G, void* const* Sigma_c,
                               int dtype, int pair_lim, int* best, double* ms, void* stream);

@@ -346,7 +346,7 @@ def sigma2b_tune(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=N
     if out is None:
         out = torch.empty_like(G)
     best = C.c_int()
-    ms = (C.c_double * 8)()
+    ms = (C.c_double * 11)()
     _check(lib().negf_sigma2b_tune(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
                                    _DT[dtype], C.byref(best), ms, _stream(stream)))
     return best.value, list(ms)
@@ -502,7 +502,7 @@ def sigma2b_batched_tune(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, pa
     Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
     Sp = (C.c_void_p * B)(*[_dev_ptr(o) for o in outs])
     best = C.c_int()
-    ms = np.zeros(8)
+    ms = np.zeros(11)
     _check(lib().negf_sigma2b_batched_tune(ctx.handle, B, n.ctypes.data_as(_IP), int(Gs[0].shape[0]),
                                            sg.ctypes.data_as(_IP), Vp, Gp, Sp, _DT[dtype], int(pair_lim),
                                            C.byref(best), _dptr(ms), _stream(stream)))

@@ -455,7 +455,7 @@ extern "C" int negf_sigma2b_batched_set_config(negf_ctx* ctx, int batch, const i
     NEGF_REQUIRE(ctx && n_b, "NULL argument");
     NEGF_REQUIRE(batch >= 1 && batch <= 65535, "batch = %d out of range [1, 65535]", batch);
     NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
-    NEGF_REQUIRE(cfg >= 0 && cfg < 8, "tile configuration %d out of range [0, 8)", cfg);
+    NEGF_REQUIRE(cfg >= 0 && cfg < 11, "tile configuration %d out of range [0, 11)", cfg);
     for (int b = 0; b < batch; ++b) NEGF_REQUIRE(n_b[b] >= 1 && n_b[b] <= 4096, "n_b[%d] out of range", b);
     std::vector<int> ns(n_b, n_b + batch);
     std::sort(ns.begin(), ns.end());

@@ -382,6 +382,221 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
     }
 }
 
+// ---------------------------------------------------------------- float64 on the vector ALUs
+// On gfx950 the float64 vector FMA sustains far more than the float64 matrix
+// cores (measured: ~72 vs ~48 TFLOP/s), so the float64 mode also has tiles that
+// form M^(i) with plain FMAs. A wave still owns one i; its 64 lanes form an 8 x 8
+// grid and lane (ty, tx) accumulates a TL x TL block of a HT x HT tile of M^(i)
+// (HT = 8 TL), rows l = l0 + ty TL + a, columns j = j0 + tx TL + b. The k-panels
+// of Gb (rows l) and G (columns j) are staged in LDS (shared by the IB waves);
+// V_i is applied to the Gb values as they are read. The epilogue is the same
+// arithmetic as in the matrix-core tile (diagonal, X', X), with the row and
+// column sums reduced across the 8 lanes of a lane row or column.
+constexpr int VK = 32;   // k-panel of the vector-ALU tiles
+
+template <int IB, int TL, int IPW>
+constexpr size_t lds_bytes_valu(int n) {
+    constexpr int HT = 8 * TL;
+    const int npt = (n + HT - 1) / HT * HT;
+    const size_t stage = 2 * VK * HT;
+    const size_t vt = (size_t)HT * (HT + 1);
+    return sizeof(double) * ((stage > vt ? stage : vt) + (size_t)IB * IPW * VK + 4 * (size_t)IB * IPW * npt);
+}
+
+// IPW values of i per wave share every Gb and G value read from LDS.
+template <int IB, int TL, int IPW>
+__device__ __forceinline__ void s2b_tile_valu(int n, int n_tau, int pair, int iblk, double sigma,
+                                              const double* __restrict__ V, const double* __restrict__ G,
+                                              double* __restrict__ Sc, unsigned char* smem_raw) {
+    constexpr int NT = IB * 64;
+    constexpr int IR = IB * IPW;
+    constexpr int HT = 8 * TL;
+    constexpr int VLD = HT + 1;
+    const int npt = (n + HT - 1) / HT * HT;
+    double* Ap = reinterpret_cast<double*>(smem_raw);        // [VK][HT]  Gb[l][k] by k
+    double* Bp = Ap + VK * HT;                               // [VK][HT]  G[k][j]
+    double* Vt = Ap;                                          // [HT][VLD] V tile (epilogue)
+    constexpr size_t STG = (2 * VK * HT > HT * VLD) ? 2 * VK * HT : HT * VLD;
+    double* Vp = Ap + STG;                                    // [IR][VK]  V_i panel
+    double* T1s = Vp + IR * VK;                               // [IR][npt]
+    double* Xs = T1s + IR * npt;
+    double* XPs = Xs + IR * npt;
+    double* Gbi = XPs + IR * npt;                             // [IR][npt] row i of Gb
+
+    int tid_ = threadIdx.x;
+    asm volatile("" : "+v"(tid_));
+    const int tid = tid_, lane = tid & 63, w = tid >> 6;
+    const int tx = lane & 7, ty = lane >> 3;
+    const int q = pair, qb = n_tau - 1 - pair;
+    const bool middle = (q == qb);
+    const long nn = (long)n * n;
+    const double* Gq = G + (long)q * nn;
+    const double* Gb = G + (long)qb * nn;
+    double* Sq = Sc + (long)q * nn;
+    double* Sqb = Sc + (long)qb * nn;
+    // this wave's rows: r = w * IPW + p, i = iblk * IR + r
+
+    for (int e = tid; e < 3 * IR * npt; e += NT) T1s[e] = 0.0;
+    for (int e = tid; e < IR * npt; e += NT) {
+        const int rr = e / npt, j = e - rr * npt;
+        const int ii = iblk * IR + rr;
+        Gbi[e] = (ii < n && j < n) ? Gb[(long)ii * n + j] : 0.0;
+    }
+
+    for (int j0 = 0; j0 < n; j0 += HT) {
+        double xcol[IPW][TL];
+#pragma unroll
+        for (int p = 0; p < IPW; ++p)
+#pragma unroll
+            for (int c = 0; c < TL; ++c) xcol[p][c] = 0.0;
+#pragma unroll 1
+        for (int l0 = 0; l0 < n; l0 += HT) {
+            double acc[IPW][TL][TL];
+#pragma unroll
+            for (int p = 0; p < IPW; ++p)
+#pragma unroll
+                for (int a = 0; a < TL; ++a)
+#pragma unroll
+                    for (int c = 0; c < TL; ++c) acc[p][a][c] = 0.0;
+#pragma unroll 1
+            for (int k0 = 0; k0 < n; k0 += VK) {
+                __syncthreads();
+                for (int e = tid; e < VK * HT; e += NT) {
+                    const int kk = e / HT, jj = e - kk * HT;
+                    const int k = k0 + kk, j = j0 + jj;
+                    Bp[e] = (k < n && j < n) ? Gq[(long)k * n + j] : 0.0;
+                }
+                for (int e = tid; e < HT * VK; e += NT) {
+                    const int ll = e / VK, kk = e - ll * VK;
+                    const int l = l0 + ll, k = k0 + kk;
+                    Ap[kk * HT + ll] = (l < n && k < n) ? Gb[(long)l * n + k] : 0.0;
+                }
+                for (int e = tid; e < IR * VK; e += NT) {
+                    const int rr = e / VK, kk = e - rr * VK;
+                    const int vi = iblk * IR + rr, k = k0 + kk;
+                    Vp[e] = (vi < n && k < n) ? V[(long)vi * n + k] : 0.0;
+                }
+                __syncthreads();
+                const int nk = min(VK, n - k0);
+                const double* Vw = Vp + w * IPW * VK;
+#pragma unroll 2
+                for (int kk = 0; kk < nk; ++kk) {
+                    double ar[TL], bv[TL];
+#pragma unroll
+                    for (int a = 0; a < TL; ++a) ar[a] = Ap[kk * HT + ty * TL + a];
+#pragma unroll
+                    for (int c = 0; c < TL; ++c) bv[c] = Bp[kk * HT + tx * TL + c];
+#pragma unroll
+                    for (int p = 0; p < IPW; ++p) {
+                        const double vk = Vw[p * VK + kk];
+#pragma unroll
+                        for (int a = 0; a < TL; ++a) {
+                            const double av = ar[a] * vk;
+#pragma unroll
+                            for (int c = 0; c < TL; ++c) acc[p][a][c] = fma(av, bv[c], acc[p][a][c]);
+                        }
+                    }
+                }
+            }
+            // V rows l0.. and columns j0.. of this tile (zero outside n)
+            __syncthreads();
+            for (int e = tid; e < HT * HT; e += NT) {
+                const int ll = e / HT, jj = e - ll * HT;
+                const int l = l0 + ll, j = j0 + jj;
+                Vt[ll * VLD + jj] = (l < n && j < n) ? V[(long)l * n + j] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < IPW; ++p) {
+                const int rr = w * IPW + p, i = iblk * IR + rr;
+                const bool iok = i < n;
+                if (l0 == j0 && tx == ty) {
+#pragma unroll
+                    for (int a = 0; a < TL; ++a) T1s[rr * npt + l0 + ty * TL + a] = acc[p][a][a];
+                }
+                double gil[TL];
+#pragma unroll
+                for (int a = 0; a < TL; ++a) {
+                    const int l = l0 + ty * TL + a;
+                    gil[a] = (iok && l < n) ? Gq[(long)i * n + l] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < TL; ++a) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < TL; ++c) {
+                        const double vm = Vt[(ty * TL + a) * VLD + tx * TL + c] * acc[p][a][c];
+                        s += Gbi[rr * npt + j0 + tx * TL + c] * vm;
+                        xcol[p][c] += gil[a] * vm;
+                    }
+                    // X'_il partial over this tile's columns: sum over the lane row (tx)
+                    s += __shfl_xor(s, 1, 64);
+                    s += __shfl_xor(s, 2, 64);
+                    s += __shfl_xor(s, 4, 64);
+                    if (tx == 0) XPs[rr * npt + l0 + ty * TL + a] += s;
+                }
+            }
+        }
+        // X_ij for this chunk's columns: sum over the lane column (ty)
+#pragma unroll
+        for (int p = 0; p < IPW; ++p)
+#pragma unroll
+            for (int c = 0; c < TL; ++c) {
+                double s = xcol[p][c];
+                s += __shfl_xor(s, 8, 64);
+                s += __shfl_xor(s, 16, 64);
+                s += __shfl_xor(s, 32, 64);
+                if (ty == 0) Xs[(w * IPW + p) * npt + j0 + tx * TL + c] = s;
+            }
+    }
+
+    // direct term D_ij = sum_l T1_il V_lj, then one store per output element
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        double d[IPW];
+#pragma unroll
+        for (int p = 0; p < IPW; ++p) d[p] = 0.0;
+        const int j = j0 + lane;
+        for (int l0 = 0; l0 < n; l0 += 16) {
+            __syncthreads();
+            for (int e = tid; e < 16 * 64; e += NT) {
+                const int ll = e >> 6, jj = e & 63;
+                const int l = l0 + ll, jg = j0 + jj;
+                Vt[ll * 65 + jj] = (l < n && jg < n) ? V[(long)l * n + jg] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int ll = 0; ll < 16; ++ll) {
+                const double vv = Vt[ll * 65 + lane];
+#pragma unroll
+                for (int p = 0; p < IPW; ++p) {
+                    const double t = (l0 + ll < n) ? T1s[(w * IPW + p) * npt + l0 + ll] : 0.0;
+                    d[p] = fma(t, vv, d[p]);
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < IPW; ++p) {
+            const int rr = w * IPW + p, i = iblk * IR + rr;
+            if (i < n && j < n) {
+                const long ij = (long)i * n + j;
+                Sq[ij] = sigma * Gq[ij] * d[p] - Xs[rr * npt + j];
+                if (!middle) Sqb[ij] = sigma * Gb[ij] * d[p] - XPs[rr * npt + j];
+            }
+        }
+    }
+}
+
+template <int IB, int TL, int IPW>
+__global__ __launch_bounds__(IB * 64, (IB == 8 ? 4 : (IPW > 1 ? 2 : 3))) void k_sigma2b_valu(int n, int n_tau, int n_iblk,
+                                                                             double sigma,
+                                                                             const double* __restrict__ V,
+                                                                             const double* __restrict__ G,
+                                                                             double* __restrict__ Sc) {
+    extern __shared__ unsigned char smem_raw[];
+    const long lb = xcd_remap(blockIdx.x, gridDim.x);
+    s2b_tile_valu<IB, TL, IPW>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, Sc, smem_raw);
+}
+
 // One workgroup per (slice pair, block of IB rows i), XCD-aware block order.
 template <int MODE, int IB, int JB, bool DB, int IPW>
 __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) void k_sigma2b(
@@ -449,6 +664,40 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) v
     }
 }
 
+// The persistent loop of k_sigma2b_batched around the float64 vector-ALU tile.
+template <int IB, int TL, int IPW>
+__global__ __launch_bounds__(IB * 64, (IB == 8 ? 4 : (IPW > 1 ? 2 : 3))) void k_sigma2b_valu_batched(
+    const S2BInst<double>* __restrict__ inst, int n_inst, int n_tau, XcdCuts cuts, int* heads) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ long s_item;
+    const int x = blockIdx.x & 7;
+    int probe = 0;
+    while (probe < 8) {
+        if (threadIdx.x == 0) {
+            const int y = (x + probe) & 7;
+            const long it = cuts.c[y] + atomicAdd(&heads[y], 1);
+            s_item = it < cuts.c[y + 1] ? it : -1;
+        }
+        __syncthreads();
+        const long it = s_item;
+        __syncthreads();
+        if (it < 0) {
+            ++probe;
+            continue;
+        }
+        int lo = 0, hi = n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (inst[mid].item0 <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const long local = it - inst[lo].item0;
+        const int nib = inst[lo].n_iblk;
+        s2b_tile_valu<IB, TL, IPW>(inst[lo].n, n_tau, (int)(local / nib), (int)(local % nib), inst[lo].sigma, inst[lo].V,
+                              inst[lo].G, inst[lo].Sc, smem_raw);
+    }
+}
+
 __global__ void k_zero_int(int* p, int count) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = 0;
@@ -484,8 +733,36 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
 // of i each unless noted) and 16-wide column blocks per chunk.
 // 0: 8 x 208 cols, 1: 8 x 112, 2: 4 x 208, 3: 4 x 112 (single-buffered staging);
 // 4: 8 x 112, 5: 4 x 208 (double-buffered staging);
-// 6: 4 waves x 2 values of i x 112 cols, 7: 4 x 2 x 64 cols (float32 and bf16 only).
-constexpr int kNumCfg = 8;
+// 6: 4 waves x 2 values of i x 112 cols, 7: 4 x 2 x 64 cols (float32 and bf16 only);
+// 8: 8 waves x 40 x 40 vector-ALU tiles, 9: 4 waves x 2 values of i x 40 x 40,
+// 10: 4 x 2 x 32 x 32 (float64 only).
+constexpr int kNumCfg = 11;
+
+template <int IB, int TL, int IPW>
+int launch_valu_cfg(int n, int n_tau, int sigma, const double* V, const double* G, double* Sc, hipStream_t st) {
+    const int n_pairs = (n_tau + 1) / 2;
+    const int n_iblk = (n + IB * IPW - 1) / (IB * IPW);
+    const size_t smem = lds_bytes_valu<IB, TL, IPW>(n);
+    if (smem > 160 * 1024) {
+        set_error("n_b = %d too large for this Sigma-2B tile configuration's LDS budget", n);
+        return NEGF_EINVAL;
+    }
+    const long blocks = (long)n_pairs * n_iblk;
+    if (blocks > 0x7fffffffL) {
+        set_error("too many workgroups");
+        return NEGF_EINVAL;
+    }
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b_valu<IB, TL, IPW>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sigma2b_valu<IB, TL, IPW>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
+                       (double)sigma, V, G, Sc);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
 
 template <int MODE, int IB, int JB, bool DB, int IPW>
 int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, const typename Cfg<MODE>::T* G,
@@ -534,11 +811,19 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
         case 5: return launch_cfg<MODE, 4, 13, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
         default:
             if constexpr (MODE == MODE_F64) {
+                const double* Vd = (const double*)V;
+                const double* Gd = (const double*)G;
+                double* Sd = (double*)Sc;
+                if (cfg == 8) return launch_valu_cfg<8, 5, 1>(n, n_tau, sigma, Vd, Gd, Sd, st);
+                if (cfg == 9) return launch_valu_cfg<4, 5, 2>(n, n_tau, sigma, Vd, Gd, Sd, st);
+                if (cfg == 10) return launch_valu_cfg<4, 4, 2>(n, n_tau, sigma, Vd, Gd, Sd, st);
                 set_error("tile configuration %d is for float32 and bf16 only", cfg);
                 return NEGF_EINVAL;
             } else {
                 if (cfg == 6) return launch_cfg<MODE, 4, 7, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
-                return launch_cfg<MODE, 4, 4, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
+                if (cfg == 7) return launch_cfg<MODE, 4, 4, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
+                set_error("tile configuration %d is for float64 only", cfg);
+                return NEGF_EINVAL;
             }
     }
 }
@@ -668,6 +953,38 @@ int launch_batched_cfg(const S2BBatch& pl, hipStream_t st) {
     return NEGF_OK;
 }
 
+template <int IB, int TL, int IPW>
+int launch_batched_valu_cfg(const S2BBatch& pl, hipStream_t st) {
+    const size_t smem = lds_bytes_valu<IB, TL, IPW>(pl.max_n);
+    if (smem + 64 > 160 * 1024) {
+        set_error("n_b = %d too large for this Sigma-2B tile configuration's LDS budget", pl.max_n);
+        return NEGF_EINVAL;
+    }
+    auto kern = k_sigma2b_valu_batched<IB, TL, IPW>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64));
+        attr_set = true;
+    }
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, IB * 64, smem));
+    if (occ < 1) {
+        set_error("Sigma-2B tile configuration does not fit a compute unit at n_b = %d", pl.max_n);
+        return NEGF_EINVAL;
+    }
+    long grid = (long)occ * pl.n_cu;
+    if (grid > pl.n_items) grid = pl.n_items;
+    if (grid < 1) return NEGF_OK;
+    XcdCuts cuts;
+    for (int x = 0; x < 9; ++x) cuts.c[x] = pl.cuts[x];
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pl.heads, 8);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(IB * 64), smem, st, (const S2BInst<double>*)pl.d_inst,
+                       pl.n_inst, pl.n_tau, cuts, pl.heads);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
 template <int MODE>
 int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
     switch (cfg) {
@@ -679,17 +996,22 @@ int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
         case 5: return launch_batched_cfg<MODE, 4, 13, true, 1>(pl, st);
         default:
             if constexpr (MODE == MODE_F64) {
+                if (cfg == 8) return launch_batched_valu_cfg<8, 5, 1>(pl, st);
+                if (cfg == 9) return launch_batched_valu_cfg<4, 5, 2>(pl, st);
+                if (cfg == 10) return launch_batched_valu_cfg<4, 4, 2>(pl, st);
                 set_error("tile configuration %d is for float32 and bf16 only", cfg);
                 return NEGF_EINVAL;
             } else {
                 if (cfg == 6) return launch_batched_cfg<MODE, 4, 7, false, 2>(pl, st);
-                return launch_batched_cfg<MODE, 4, 4, false, 2>(pl, st);
+                if (cfg == 7) return launch_batched_cfg<MODE, 4, 4, false, 2>(pl, st);
+                set_error("tile configuration %d is for float64 only", cfg);
+                return NEGF_EINVAL;
             }
     }
 }
 
 // rows i per workgroup of a configuration
-int cfg_rows(int cfg) { return (cfg == 0 || cfg == 1 || cfg == 4 || cfg >= 6) ? 8 : 4; }
+int cfg_rows(int cfg) { return (cfg == 2 || cfg == 3 || cfg == 5) ? 4 : 8; }
 
 std::string batch_key(int mode, const std::vector<int>& n) {
     std::string k = "s2bB_" + std::to_string(mode);

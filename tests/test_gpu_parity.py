@@ -61,15 +61,21 @@ def test_sigma2b_f64(ctx, torch_mod, n, n_tau):
     assert relerr(host(out), ref) < TOL64
 
 
-@pytest.mark.parametrize("cfg", range(8))
+F64_ONLY, LOWP_ONLY = (8, 9, 10), (6, 7)
+
+
+@pytest.mark.parametrize("cfg", range(11))
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_sigma2b_every_tile_config(ctx, torch_mod, cfg, dtype):
     """Every tile configuration the tuner can pick, on a size with several column
     chunks (n > 208) and on a ragged small size."""
-    if dtype == "f64" and cfg >= 6:
+    if (dtype == "f64" and cfg in LOWP_ONLY) or (dtype != "f64" and cfg in F64_ONLY):
+        wt = torch_mod.float64 if dtype == "f64" else torch_mod.float32
         with pytest.raises(negf.NegfError):
             negf.sigma2b_set_config(ctx, 37, dtype, cfg)
-            negf.sigma2b(ctx, dev(torch_mod, _pos_V(37, 11)), dev(torch_mod, W.random_symmetric_slices(37, 5, 12)), 2)
+            negf.sigma2b(ctx, dev(torch_mod, _pos_V(37, 11), wt), dev(torch_mod, W.random_symmetric_slices(37, 5, 12), wt),
+                         2, dtype=dtype)
+        negf.sigma2b_set_config(ctx, 37, dtype, 1)
         return
     for n, n_tau in ((221, 3), (37, 5), (9, 4)):
         V = _pos_V(n, 11)
@@ -91,7 +97,8 @@ def test_sigma2b_tuner(ctx, torch_mod):
     V = _pos_V(n, 13)
     G = W.random_symmetric_slices(n, n_tau, 14)
     best, ms = negf.sigma2b_tune(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
-    assert 0 <= best < 6 and ms[best] > 0 and all(m > 0 for m in ms[:6]) and all(m == -1.0 for m in ms[6:])
+    assert best not in LOWP_ONLY and ms[best] > 0
+    assert all(m > 0 for m in ms[:6] + ms[8:]) and all(m == -1.0 for m in ms[6:8])
     out = negf.sigma2b(ctx, dev(torch_mod, V), dev(torch_mod, G), 2)
     assert relerr(host(out), S.sigma2b(V, G, 2)) < TOL64
 

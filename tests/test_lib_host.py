@@ -114,7 +114,7 @@ def test_batched_entry_points_reject_bad_arguments(L):
     assert rc == negf.EINVAL and b"alias" in L.negf_last_error()
     rc = L.negf_sigma2b_batched(C.c_void_p(1), 0, n, 5, sg, ptrs, ptrs, outs, 0, None)
     assert rc == negf.EINVAL
-    rc = L.negf_sigma2b_batched_set_config(C.c_void_p(1), 2, n, 0, 8)
+    rc = L.negf_sigma2b_batched_set_config(C.c_void_p(1), 2, n, 0, 11)
     assert rc == negf.EINVAL
     rc = L.negf_hf_batched(C.c_void_p(1), 0, 10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 2.0, 2, 10.0, 1e-10,
                            10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None, None, None, None)
