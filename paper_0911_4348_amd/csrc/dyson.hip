@@ -25,6 +25,7 @@
 // is <= 1 (forward decay or a prefix sum with e^(xi tau) for xi < 0, and the
 // mirror images backwards). G0 itself is added in the same pass.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -258,69 +259,104 @@ __device__ void make_stencil(int p, int q, int n_tau, int kind, int block, const
     }
 }
 
-// Out[p] = sum_q sum_m wt_m Sc[node_m] G[q] for one 64 x 64 output tile of slice p.
-template <class T>
-__global__ __launch_bounds__(256) void k_conv_direct(int n, int n_tau, int kind, int block,
-                                                     const double* __restrict__ tau, const double* __restrict__ w,
-                                                     const T* __restrict__ Sc, const T* __restrict__ G,
-                                                     T* __restrict__ Out) {
-    __shared__ T As[16][66];
-    __shared__ T Bs[16][66];
-    __shared__ Stencil sst;
+// Out[p] = sum_q sum_m wt_m Sc[node_m] G[q] for a strip of 64 rows of slice p and
+// up to 2 x JTW x 16 columns starting at c0. The interpolated Sigma_c rows (the A
+// operand) are formed once per (p, q, k-panel) and used against the whole strip
+// of columns, so the kernel is bound by the matrix cores rather than by the
+// reads of the interpolation nodes. 8 waves: wave w owns row tile w & 3 and the
+// column tiles (w >> 2) + 2 t. Stencils of 32 values of q are built at a time.
+template <class T, int JTW>
+__global__ __launch_bounds__(512) void k_conv_strip(int n, int n_tau, int kind, int block,
+                                                    const double* __restrict__ tau, const double* __restrict__ w,
+                                                    const T* __restrict__ Sc, const T* __restrict__ G,
+                                                    T* __restrict__ Out, int c0, int c1) {
+    constexpr int BK = 16, CWP = 2 * JTW * 16;
+    __shared__ T As[BK][65];
+    __shared__ T Bs[BK][CWP + 1];
+    __shared__ Stencil sst[32];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wr = wv >> 1, wc = wv & 1;
-    const int p = blockIdx.z, m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int rt = wv & 3, cg = wv >> 2;
+    // XCD-aware order: each XCD takes a contiguous range of (p, strip) so that the
+    // blocks resident on it share the G panels and nearby Sigma_c nodes in its L2
+    const int nstrip = (n + 63) / 64;
+    const long nblk = (long)gridDim.x;
+    const long xb = blockIdx.x & 7, kb = blockIdx.x >> 3;
+    const long lb = xb * (nblk >> 3) + (xb < (nblk & 7) ? xb : (nblk & 7)) + kb;
+    const int p = (int)(lb / nstrip), m0 = (int)(lb % nstrip) * 64;
     const long nn = (long)n * n;
-    typename Mma<T>::acc_t acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = Mma<T>::zero();
-    for (int q = 0; q < n_tau; ++q) {
-        __syncthreads();
-        if (tid == 0) make_stencil(p, q, n_tau, kind, block, tau, w, sst);
-        __syncthreads();
-        const int cnt = sst.cnt;
-        if (cnt == 0) continue;
-        const T* Gq = G + (long)q * nn;
-        for (int k0 = 0; k0 < n; k0 += 16) {
-            T ra[4], rb[4];
-            {
-                const int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
-                for (int e = 0; e < 4; ++e) {
-                    const int k = kb + e;
-                    double v = 0.0;
-                    if (m < n && k < n)
-                        for (int c = 0; c < cnt; ++c) v += sst.wt[c] * (double)Sc[(long)sst.node[c] * nn + (long)m * n + k];
-                    ra[e] = (T)v;
-                }
-                const int kk = k0 + (tid >> 4), nb = n0 + (tid & 15) * 4;
-                for (int e = 0; e < 4; ++e) {
-                    const int j = nb + e;
-                    rb[e] = (kk < n && j < n) ? Gq[(long)kk * n + j] : T(0);
-                }
-            }
-            __syncthreads();
-            for (int e = 0; e < 4; ++e) As[(tid & 3) * 4 + e][tid >> 2] = ra[e];
-            for (int e = 0; e < 4; ++e) Bs[tid >> 4][(tid & 15) * 4 + e] = rb[e];
-            __syncthreads();
+    typename Mma<T>::acc_t acc[JTW];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int kk = ks * 4 + (lane >> 4);
-                T a0 = As[kk][wr * 32 + (lane & 15)], a1 = As[kk][wr * 32 + 16 + (lane & 15)];
-                T b0 = Bs[kk][wc * 32 + (lane & 15)], b1 = Bs[kk][wc * 32 + 16 + (lane & 15)];
-                acc[0][0] = Mma<T>::mma(a0, b0, acc[0][0]);
-                acc[0][1] = Mma<T>::mma(a0, b1, acc[0][1]);
-                acc[1][0] = Mma<T>::mma(a1, b0, acc[1][0]);
-                acc[1][1] = Mma<T>::mma(a1, b1, acc[1][1]);
+    for (int t = 0; t < JTW; ++t) acc[t] = Mma<T>::zero();
+    for (int q0 = 0; q0 < n_tau; q0 += 32) {
+        __syncthreads();
+        if (tid < 32) {
+            if (q0 + tid < n_tau) make_stencil(p, q0 + tid, n_tau, kind, block, tau, w, sst[tid]);
+            else sst[tid].cnt = 0;
+        }
+        __syncthreads();
+        const int qn = min(32, n_tau - q0);
+        for (int qq = 0; qq < qn; ++qq) {
+            const int cnt = sst[qq].cnt;
+            if (cnt == 0) continue;
+            const T* Gq = G + (long)(q0 + qq) * nn;
+            for (int k0 = 0; k0 < n; k0 += BK) {
+                for (int e = tid; e < 64 * BK; e += 512) {
+                    const int m = e / BK, kk = e - m * BK;
+                    const int row = m0 + m, k = k0 + kk;
+                    double v = 0.0;
+                    if (row < n && k < n)
+                        for (int c = 0; c < cnt; ++c)
+                            v += sst[qq].wt[c] * (double)Sc[(long)sst[qq].node[c] * nn + (long)row * n + k];
+                    As[kk][m] = (T)v;
+                }
+                for (int e = tid; e < BK * CWP; e += 512) {
+                    const int kk = e / CWP, j = e - kk * CWP;
+                    const int k = k0 + kk, col = c0 + j;
+                    Bs[kk][j] = (k < n && col < c1) ? Gq[(long)k * n + col] : T(0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int ks = 0; ks < BK / 4; ++ks) {
+                    const int kk = ks * 4 + (lane >> 4);
+                    const T a = As[kk][rt * 16 + (lane & 15)];
+#pragma unroll
+                    for (int t = 0; t < JTW; ++t) acc[t] = Mma<T>::mma(a, Bs[kk][(cg + 2 * t) * 16 + (lane & 15)], acc[t]);
+                }
+                __syncthreads();
             }
         }
     }
-    for (int mi = 0; mi < 2; ++mi)
-        for (int ni = 0; ni < 2; ++ni)
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wr * 32 + mi * 16 + Mma<T>::row(lane, r);
-                const int col = n0 + wc * 32 + ni * 16 + (lane & 15);
-                if (row < n && col < n) Out[(long)p * nn + (long)row * n + col] = acc[mi][ni][r];
-            }
+#pragma unroll
+    for (int t = 0; t < JTW; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + rt * 16 + Mma<T>::row(lane, r);
+            const int col = c0 + (cg + 2 * t) * 16 + (lane & 15);
+            if (row < n && col < c1) Out[(long)p * nn + (long)row * n + col] = acc[t][r];
+        }
+}
+
+template <class T>
+int conv_strip_launch(int n, int n_tau, int kind, int block, const double* tau, const double* w, const T* Sc,
+                      const T* G, T* Out, hipStream_t st) {
+    const int ct = (n + 15) / 16;                 // column tiles
+    const int jtw = (ct + 1) / 2;
+
+    const dim3 grid((unsigned)(((n + 63) / 64) * n_tau));
+    auto go = [&](auto jt_const) -> int {
+        constexpr int JT = decltype(jt_const)::value;
+        for (int c0 = 0; c0 < n; c0 += 2 * JT * 16) {
+            const int c1 = min(n, c0 + 2 * JT * 16);
+            hipLaunchKernelGGL((k_conv_strip<T, JT>), grid, dim3(512), 0, st, n, n_tau, kind, block, tau, w, Sc, G,
+                               Out, c0, c1);
+            LAUNCH_CHECK();
+        }
+        return NEGF_OK;
+    };
+    if (jtw <= 2) return go(std::integral_constant<int, 2>());
+    if (jtw <= 4) return go(std::integral_constant<int, 4>());
+    if (jtw <= 7) return go(std::integral_constant<int, 7>());
+    return go(std::integral_constant<int, 13>());
 }
 
 // ------------------------------------------------------------ eigenbasis recurrences
@@ -601,10 +637,8 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
                            I1 + (long)M * nn);
         LAUNCH_CHECK();
     } else {
-        dim3 grid((n + 63) / 64, (n + 63) / 64, n_tau);
-        hipLaunchKernelGGL((k_conv_direct<T>), grid, dim3(256), 0, st, n, n_tau, tg->kind,
-                           tg->kind == NEGF_TAU_POWER ? tg->block : 1, d_tau, d_w, Sc, G_in, I1);
-        LAUNCH_CHECK();
+        NEGF_TRY(conv_strip_launch<T>(n, n_tau, tg->kind, tg->kind == NEGF_TAU_POWER ? tg->block : 1, d_tau, d_w,
+                                      Sc, G_in, I1, st));
         NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), St, n, 0, G_in, n, nn, T(1), I1, n, nn, I1, n, nn, n_tau));
     }
 
