@@ -1,16 +1,21 @@
 """Benchmark of the FE-DVR second-Born hot path on one MI355X.
 
-Workload: the Sigma-2B microbenchmark system, n_b = 199 (40 elements x 6 GLL
-points on [-40, 40]), 1025 tau points on [0, 50], seeded synthetic symmetric
-G(tau) (entries ~ N(0, 0.1^2) decaying as e^(-tau)). One step = one full
-second-Born iteration on that input: negf_sigma2b over all slices, then
-negf_dyson_step (HF static term, Fourier-route Sigma_c convolution,
-eigenbasis G0 convolution, mixing, symmetrisation, float64 energy).
+Default workload: the Sigma-2B microbenchmark system, n_b = 199 (40 elements x 6 GLL
+points on [-40, 40]), 1025 tau points on [0, 50], seeded synthetic symmetric G(tau)
+(entries ~ N(0, 0.1^2) decaying as e^(-tau)). One step = one full second-Born
+iteration on that input: negf_sigma2b over all slices, then negf_dyson_step (HF
+static term, Fourier-route Sigma_c convolution, eigenbasis G0 convolution, mixing,
+symmetrisation, float64 energy).
 
-The JSON line reports Sigma-2B algorithmic GFLOP/s over the whole timed
-region (value), the roofline of the Sigma-2B kernel from HIP events recorded
-on the stream it runs on, and the FP64 CPU oracle timed on a bounded sample
-of the same workload.
+The JSON line reports Sigma-2B algorithmic GFLOP/s over the whole timed region
+(value), the roofline of the Sigma-2B kernel from HIP events recorded on the stream
+it runs on, the SCF time to 1e-6 Ha of the plain float64 path, the mixed forms and
+the learned start on a held-out potential, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+--workload scan: the 64-instance linear H3+ bond-length scan to 1e-6 Ha (batched or
+one instance after another); --workload h3p: linear H3+ on the 2049-point power mesh
+to 1e-6 Ha (float64 and the mixed form). Each takes minutes.
 """
 from __future__ import annotations
 

@@ -377,71 +377,141 @@ __global__ void k_scan_tables(int n, int n_tau, const double* __restrict__ tau, 
 }
 
 // Out[p][k][j] = Q_p[-g_k, In[.][k][j]] - g_k(tau_p) C[j][k]: the eigenbasis form
-// of G0 + Q[G0, I1] before the final rotation by C.
+// of G0 + Q[G0, I1] before the final rotation by C, as a forward and a backward
+// recurrence over tau per element (k, j). The tau axis is cut into 16 chunks and
+// a workgroup holds 16 elements x 16 chunks: each chunk first runs its recurrence
+// from zero to get its affine aggregate (acc_out = d acc_in + a), the aggregates
+// are folded in LDS to give every chunk its starting value, and the chunk then
+// runs again writing the outputs.
 template <class T>
-__global__ __launch_bounds__(256) void k_eig_scan(int n, int n_tau, const T* __restrict__ In, T* __restrict__ Out,
-                                                  const double* __restrict__ w, const double* __restrict__ hL,
-                                                  const double* __restrict__ hR, const double* __restrict__ Ea,
-                                                  const double* __restrict__ Eb, const double* __restrict__ dec,
-                                                  const double* __restrict__ cpre, const double* __restrict__ eps,
-                                                  double mu, const double* __restrict__ C) {
+__global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, const T* __restrict__ In, T* __restrict__ Out,
+                                                          const double* __restrict__ w, const double* __restrict__ hL,
+                                                          const double* __restrict__ hR, const double* __restrict__ Ea,
+                                                          const double* __restrict__ Eb, const double* __restrict__ dec,
+                                                          const double* __restrict__ cpre,
+                                                          const double* __restrict__ eps, double mu,
+                                                          const double* __restrict__ C) {
+    constexpr int NCH = 16, NE = 16;
+    __shared__ double sd[NCH][NE + 1], sa[NCH][NE + 1];
+    const int el = threadIdx.x & (NE - 1), ch = threadIdx.x / NE;
     const long nn = (long)n * n;
-    const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (e >= nn) return;
-    const int k = (int)(e / n), j = (int)(e % n);
-    const bool pos = eps[k] - mu >= 0.0;
-    const double c = cpre[k];
-    const int M = n_tau - 1;
-    double acc = 0.0;
-    if (pos) {
-        for (int p = 0; p <= M; ++p) {
-            const double b = (double)In[(long)p * nn + e];
-            Out[(long)p * nn + e] = (T)(c * (acc + hL[p] * b));
-            if (p < M) acc = dec[(long)p * n + k] * (acc + w[p] * b);
+    const long e = (long)blockIdx.x * NE + el;
+    const bool ok = e < nn;
+    const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
+    const bool pos = ok && eps[k] - mu >= 0.0;
+    const double c = ok ? cpre[k] : 0.0;
+    const int M = n_tau - 1, P = n_tau;
+    const int p0 = (int)((long)ch * P / NCH), p1 = (int)((long)(ch + 1) * P / NCH);
+    auto fold_fwd = [&](double& start) {
+        start = 0.0;
+        for (int cc = 0; cc < ch; ++cc) start = sd[cc][el] * start + sa[cc][el];
+    };
+    auto fold_bwd = [&](double& start) {
+        start = 0.0;
+        for (int cc = NCH - 1; cc > ch; --cc) start = sd[cc][el] * start + sa[cc][el];
+    };
+    // ---- forward recurrence (lower part of the convolution)
+    {
+        double acc = 0.0, d = 1.0;
+        if (ok) {
+            for (int p = p0; p < p1; ++p) {
+                const double b = (double)In[(long)p * nn + e];
+                if (pos) {
+                    if (p < M) {
+                        const double dp = dec[(long)p * n + k];
+                        acc = dp * (acc + w[p] * b);
+                        d *= dp;
+                    }
+                } else {
+                    acc += w[p] * Ea[(long)p * n + k] * b;
+                }
+            }
         }
-    } else {
-        for (int p = 0; p <= M; ++p) {
-            const double b = (double)In[(long)p * nn + e];
-            const double ea = Ea[(long)p * n + k];
-            Out[(long)p * nn + e] = (T)(c * Eb[(long)p * n + k] * (acc + hL[p] * ea * b));
-            acc += w[p] * ea * b;
+        sd[ch][el] = d;
+        sa[ch][el] = acc;
+        __syncthreads();
+        fold_fwd(acc);
+        if (ok) {
+            for (int p = p0; p < p1; ++p) {
+                const double b = (double)In[(long)p * nn + e];
+                if (pos) {
+                    Out[(long)p * nn + e] = (T)(c * (acc + hL[p] * b));
+                    if (p < M) acc = dec[(long)p * n + k] * (acc + w[p] * b);
+                } else {
+                    const double ea = Ea[(long)p * n + k];
+                    Out[(long)p * nn + e] = (T)(c * Eb[(long)p * n + k] * (acc + hL[p] * ea * b));
+                    acc += w[p] * ea * b;
+                }
+            }
         }
+        __syncthreads();
     }
-    const double cjk = C[(long)j * n + k];
-    acc = 0.0;
-    if (pos) {
-        for (int p = M; p >= 0; --p) {
-            const double b = (double)In[(long)p * nn + e];
-            const double eb = Eb[(long)p * n + k], ea = Ea[(long)p * n + k];
-            const double R = c * ea * (acc + hR[p] * eb * b);
-            acc += w[p] * eb * b;
-            const double L = (double)Out[(long)p * nn + e];
-            Out[(long)p * nn + e] = (T)(-L + R - c * ea * cjk);
+    // ---- backward recurrence (upper part), combined with the forward result
+    {
+        double acc = 0.0, d = 1.0;
+        if (ok) {
+            for (int p = p1 - 1; p >= p0; --p) {
+                const double b = (double)In[(long)p * nn + e];
+                if (pos) {
+                    acc += w[p] * Eb[(long)p * n + k] * b;
+                } else if (p > 0) {
+                    const double dp = dec[(long)(p - 1) * n + k];
+                    acc = dp * (acc + w[p] * b);
+                    d *= dp;
+                }
+            }
         }
-    } else {
-        for (int p = M; p >= 0; --p) {
-            const double b = (double)In[(long)p * nn + e];
-            const double R = c * (acc + hR[p] * b);
-            if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b);
-            const double L = (double)Out[(long)p * nn + e];
-            Out[(long)p * nn + e] = (T)(-L + R - c * Eb[(long)p * n + k] * cjk);
+        sd[ch][el] = d;
+        sa[ch][el] = acc;
+        __syncthreads();
+        fold_bwd(acc);
+        if (ok) {
+            const double cjk = C[(long)j * n + k];
+            for (int p = p1 - 1; p >= p0; --p) {
+                const double b = (double)In[(long)p * nn + e];
+                const double L = (double)Out[(long)p * nn + e];
+                if (pos) {
+                    const double eb = Eb[(long)p * n + k], ea = Ea[(long)p * n + k];
+                    const double R = c * ea * (acc + hR[p] * eb * b);
+                    acc += w[p] * eb * b;
+                    Out[(long)p * nn + e] = (T)(-L + R - c * ea * cjk);
+                } else {
+                    const double R = c * (acc + hR[p] * b);
+                    if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b);
+                    Out[(long)p * nn + e] = (T)(-L + R - c * Eb[(long)p * n + k] * cjk);
+                }
+            }
         }
     }
 }
 
+// G[s] <- (G[s] + G[s]^T)/2 for every slice, by pairs of 32 x 32 tiles (I, J),
+// I <= J: both tiles are read row-wise into LDS and written back row-wise.
+// grid.x = tile pair, grid.y = slice.
 template <class T>
-__global__ void k_symmetrize(int n, long nslices, T* G) {
-    const long nn = (long)n * n;
-    const long tot = nn * nslices;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-        const long s = e / nn, r = e % nn;
-        const int i = (int)(r / n), j = (int)(r % n);
-        if (i < j) {
-            T* g = G + s * nn;
-            const T v = T(0.5) * (g[(long)i * n + j] + g[(long)j * n + i]);
-            g[(long)i * n + j] = v;
-            g[(long)j * n + i] = v;
-        }
+__global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, T* G) {
+    __shared__ T A[32][33], B[32][33];
+    // tile pair index -> (I, J), I <= J, row-major over the upper triangle of tiles
+    int r = blockIdx.x, I = 0;
+    while (r >= nt - I) {
+        r -= nt - I;
+        ++I;
+    }
+    const int J = I + r;
+    T* g = G + (long)blockIdx.y * n * n;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int ra = I * 32 + yy, ca = J * 32 + tx;
+        A[yy][tx] = (ra < n && ca < n) ? g[(long)ra * n + ca] : T(0);
+        const int rb = J * 32 + yy, cb = I * 32 + tx;
+        B[yy][tx] = (rb < n && cb < n) ? g[(long)rb * n + cb] : T(0);
+    }
+    __syncthreads();
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int ra = I * 32 + yy, ca = J * 32 + tx;
+        if (ra < n && ca < n) g[(long)ra * n + ca] = T(0.5) * (A[yy][tx] + B[tx][yy]);
+        const int rb = J * 32 + yy, cb = I * 32 + tx;
+        if (I != J && rb < n && cb < n) g[(long)rb * n + cb] = T(0.5) * (B[yy][tx] + A[tx][yy]);
     }
 }
 
@@ -661,13 +731,19 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
     hipLaunchKernelGGL(k_scan_tables, dim3(grid_for((long)n * n_tau)), dim3(256), 0, st, n, n_tau, d_tau, tg->beta,
                        eps, mu, Ea, Eb, dec, cpre);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_eig_scan<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, n, n_tau, It, I1, d_w,
-                       d_hL, d_hR, Ea, Eb, dec, cpre, eps, mu, C);
+    hipLaunchKernelGGL((k_eig_scan_chunked<T>), dim3((unsigned)((nn + 15) / 16)), dim3(256), 0, st, n, n_tau, It, I1,
+                       d_w, d_hL, d_hR, Ea, Eb, dec, cpre, eps, mu, C);
     LAUNCH_CHECK();
     NEGF_TRY(gemm<T>(st, false, false, n, n, n, (T)alpha, Ct, n, 0, I1, n, nn, (T)(1.0 - alpha), G_in, n, nn, G_out,
                      n, nn, n_tau));
     if (symmetrize) {
-        hipLaunchKernelGGL((k_symmetrize<T>), dim3(grid_for(nn * n_tau)), dim3(256), 0, st, n, (long)n_tau, G_out);
+        const int nt = (n + 31) / 32;
+        for (int s0 = 0; s0 < n_tau; s0 += 65535) {
+            const int ns = min(65535, n_tau - s0);
+            hipLaunchKernelGGL((k_symmetrize<T>), dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)ns), dim3(256), 0, st,
+                               n, nt, G_out + (long)s0 * nn);
+            LAUNCH_CHECK();
+        }
         LAUNCH_CHECK();
     }
     return NEGF_OK;
