@@ -69,8 +69,10 @@ int negf_version(void);
 /* ------------------------------------------------------------------ context */
 typedef struct negf_ctx negf_ctx;
 
-/* Create a context bound to GPU `device` (scratch buffers, Fourier tables).
- * *out receives the handle. Errors: NEGF_EINVAL (out NULL), NEGF_ENODEV. */
+/* Create a context bound to GPU `device` (scratch buffers, Fourier tables, tuned
+ * tile choices, the SCF driver's own stream). *out receives the handle. A context
+ * is used by one host thread at a time; calls on it are ordered on the caller's
+ * stream. Errors: NEGF_EINVAL (out NULL), NEGF_ENODEV. */
 int negf_ctx_create(int device, negf_ctx** out);
 /* Release the context's device scratch. NULL is accepted. */
 int negf_ctx_destroy(negf_ctx* ctx);

@@ -416,7 +416,7 @@ def _records(logs, base, count):
 
 def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
         conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
-        allow_noconv=False, guess=None, guess_scale=1.0, graphs=True, tune=False, progress=False,
+        allow_noconv=False, guess=None, guess_scale=1.0, graphs=True, tune=True, progress=False,
         stream=None) -> SCFOut:
     """negf_scf for a workloads.System (guess: learned-guess parameters on the device)."""
     out = scf_batched(ctx, [sysd], alpha=alpha, tol=tol, max_iter=max_iter, fixed_iters=fixed_iters, dtype=dtype,
@@ -429,7 +429,7 @@ def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, d
 
 def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
                 conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
-                allow_noconv=False, guess=None, guess_scale=1.0, tune=False, graphs=True, single=False,
+                allow_noconv=False, guess=None, guess_scale=1.0, tune=True, graphs=True, single=False,
                 progress=False, stream=None):
     """negf_scf_batched (single=True: negf_scf) for a list of workloads.System; returns a list of SCFOut."""
     torch = _torch()

@@ -80,7 +80,6 @@ struct Sys {
 struct GraphSlot {
     std::string key;
     hipGraphExec_t exec = nullptr;
-    bool seen = false;       // key already run once directly
     void drop() {
         if (exec) (void)hipGraphExecDestroy(exec);
         exec = nullptr;
@@ -97,7 +96,6 @@ int run_segment(GraphSlot& slot, const std::string& key, bool graphs, GraphSlot&
         slot.drop();
         other.drop();
         slot.key = key;
-        slot.seen = true;
         return body();
     }
     if (!slot.exec) {
