@@ -35,8 +35,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "5620dec1b474129a"
-TRAFFIC_F64_NB199 = {0: 2229980254, 1: 657040539, 2: 656742480, 3: 657729701, 4: 658098249, 5: 656810587}
+TRAFFIC_SRC_SHA256 = "2e8c2c2b7d5d9e60"
+TRAFFIC_F64_NB199 = {0: 2990155297, 1: 657084869, 2: 656773328, 3: 657852130, 4: 657708808, 5: 656849051,
+                     8: 664052828, 9: 664877890, 10: 663966498}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):
