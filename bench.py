@@ -9,7 +9,8 @@ symmetrisation, float64 energy).
 
 The JSON line reports Sigma-2B algorithmic GFLOP/s over the whole timed region
 (value), the roofline of the Sigma-2B kernel from HIP events recorded on the stream
-it runs on, the SCF time to 1e-6 Ha of the plain float64 path, the mixed forms and
+it runs on (against the datasheet peak, with the measured sustained rate of the same
+matrix-core operation beside it as measured_ceiling), the SCF time to 1e-6 Ha of the plain float64 path, the mixed forms and
 the learned start on a held-out potential, and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
 
@@ -35,9 +36,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "2e8c2c2b7d5d9e60"
-TRAFFIC_F64_NB199 = {0: 2990155297, 1: 657084869, 2: 656773328, 3: 657852130, 4: 657708808, 5: 656849051,
-                     8: 664052828, 9: 664877890, 10: 663966498}
+TRAFFIC_SRC_SHA256 = "f227d761d053d3a8"
+TRAFFIC_F64_NB199 = {0: 656744793, 1: 657080344, 2: 656802977, 3: 658109172, 4: 657756080, 5: 1166288718,
+                     8: 663916869, 9: 664902965, 10: 663901757}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):
@@ -335,7 +336,7 @@ def main():
                      "algorithmic_bytes": int(sigma2b_bytes(n, n_tau, elem))},
         "sigma2b_ms": round(sig_avg, 3),
         "sigma2b_tuner": {"configs": ["8i x 208col", "8i x 112col", "4i x 208col", "4i x 112col",
-                                      "8i x 112col 2-stage", "4i x 208col 2-stage", "4w x 2i x 112col",
+                                      "8i x 112col 2-stage", "8i x 208col 2-stage", "4w x 2i x 112col",
                                       "4w x 2i x 64col", "f64 VALU 8i x 40x40", "f64 VALU 4w x 2i x 40x40",
                                       "f64 VALU 4w x 2i x 32x32"],
                           "ms": [round(m, 3) for m in tune_ms], "chosen": best},
@@ -343,6 +344,13 @@ def main():
         "sigma2b_hbm_GBps": round(sigma2b_bytes(n, n_tau, elem) / (sig_avg * 1e-3) / 1e9, 1),
         "dyson_gflops": round(dyson_flops(n, M) / (float(np.mean(dy_ms)) * 1e-3) / 1e9, 1),
     }
+    # measured ceiling of the same matrix-core operation on this GPU (after the timed region)
+    ceil_tf, ceil_ghz = negf.matrix_rate(ctx, args.dtype)
+    out["roofline"]["measured_ceiling"] = {
+        "value": round(ceil_tf, 2), "unit": "TFLOP/s", "clock_ghz": round(ceil_ghz, 3),
+        "frac": round(achieved / ceil_tf, 4) if ceil_tf > 0 else None,
+        "how": "negf_matrix_rate: 8 independent chains of the kernel's MFMA shape per wave, register "
+               "operands, 8 waves per SIMD on every CU"}
     if args.copy_calibration > 0:
         nel = args.copy_calibration // 8
         src = torch.ones(nel, dtype=torch.float64, device=dev)

@@ -188,12 +188,23 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
 
 /* Pin the negf_sigma2b tile configuration for (dtype, n_b) in this context:
  * 0..3 = (8 or 4 values of i per workgroup) x (208- or 112-column chunks) with
- * single-buffered k-panels; 4, 5 = 8 x 112 and 4 x 208 with double-buffered
+ * single-buffered k-panels; 4, 5 = 8 x 112 and 8 x 208 with double-buffered
  * k-panels; 6, 7 (NEGF_F32 and NEGF_BF16 only) = 4 waves with two values of i
  * each x 112- or 64-column chunks; 8, 9, 10 (NEGF_F64 only) = float64 vector-ALU
  * tiles: 8 waves x 40 x 40 blocks of M^(i), 4 waves with two values of i each x
  * 40 x 40 or 32 x 32 blocks. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
+
+/* Sustained rate of the matrix-core operation the Sigma-2B kernels issue for
+ * `dtype` (NEGF_F64: 16x16x4 float64, NEGF_F32: 16x16x4 float32, NEGF_BF16:
+ * 16x16x32 bf16 with float32 accumulation), measured on the context's GPU: a
+ * kernel of 8 independent accumulator chains per wave with register operands,
+ * 8 waves per SIMD on every compute unit, run twice (the faster run counts).
+ * host out: tflops (TFLOP/s), clock_ghz (median shader clock of the waves,
+ * from the core-clock and fixed-rate counters). A measured ceiling to quote
+ * beside the datasheet peak; not part of the method. Uses context scratch
+ * (a few MB). Synchronises. */
+int negf_matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* clock_ghz, void* stream);
 
 /* Sigma-2B (as negf_sigma2b) for `batch` systems of any sizes n_b[b] on one
  * tau grid of n_tau points, in a single persistent kernel launch: work items

@@ -105,6 +105,7 @@ _SIGS = {
     "negf_sigma2b_batched_set_config": (C.c_int, [_VP, C.c_int, _IP, C.c_int, C.c_int]),
     "negf_sigma2b_batched_tune": (C.c_int, [_VP, C.c_int, _IP, C.c_int, _IP, _VP, _VP, _VP, C.c_int, C.c_int,
                                             _IP, _DP, _VP]),
+    "negf_matrix_rate": (C.c_int, [_VP, C.c_int, _DP, _DP, _VP]),
     "negf_mlp_param_count": (C.c_int, [_IP]),
     "negf_mlp_features": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP, C.c_double,
                                     C.c_int, _VP, _VP, _VP, _VP, _VP]),
@@ -467,6 +468,15 @@ def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed
         _check(rc)
     return [SCFOut(Gs[b], float(E[b]), float(N[b]), int(it[b]), float(hE[b]), float(hmu[b]),
                    _records(logs, b * cap, int(ln[b])), int(stat[b])) for b in range(B)]
+
+
+def matrix_rate(ctx: Context, dtype="f64", stream=None):
+    """Measured sustained rate (TFLOP/s) of the matrix-core operation the
+    Sigma-2B kernels use for ``dtype``, and the shader clock (GHz) it ran at."""
+    tf = C.c_double(0.0)
+    ghz = C.c_double(0.0)
+    _check(lib().negf_matrix_rate(ctx.handle, _DT[dtype], C.byref(tf), C.byref(ghz), _stream(stream)))
+    return tf.value, ghz.value
 
 
 def sigma2b_batched(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, stream=None):

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnegf.so")
 
-SOURCES = ["abi.cpp", "gemm.hip", "hf.hip", "sigma2b.hip", "dyson.hip", "scf.cpp", "mlp.hip"]
+SOURCES = ["abi.cpp", "gemm.hip", "hf.hip", "sigma2b.hip", "dyson.hip", "scf.cpp", "mlp.hip", "probe.hip"]
 ARCH = os.environ.get("NEGF_OFFLOAD_ARCH", "gfx950")
 
 

@@ -472,6 +472,14 @@ extern "C" int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cf
     return sigma2b_set_cfg(ctx, dtype, n_b, cfg);
 }
 
+extern "C" int negf_matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* clock_ghz, void* stream) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(tflops && clock_ghz, "NULL output");
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    NEGF_TRY(bind_device(ctx));
+    return matrix_rate(ctx, dtype, tflops, clock_ghz, (hipStream_t)stream);
+}
+
 // ============================================================== Dyson / energy
 namespace {
 int check_dyson_common(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, int dtype) {

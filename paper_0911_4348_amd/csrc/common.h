@@ -77,6 +77,9 @@ int s2b_batch_prepare(negf_ctx* ctx, const char* tag, int dtype, int batch, cons
                       const int* sigma, const void* const* V, const void* const* G, void* const* Sc, int pair_lim,
                       S2BBatch* plan, hipStream_t st);
 int s2b_batch_launch(const S2BBatch& plan, hipStream_t st);
+// Sustained rate (TFLOP/s) of the dtype's MFMA shape and the shader clock (GHz)
+// it ran at, from a kernel of independent MFMA chains; synchronises.
+int matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* ghz, hipStream_t st);
 int s2b_batch_tune(negf_ctx* ctx, int dtype, int batch, const int* n, int n_tau, const int* sigma,
                    const void* const* V, const void* const* G, void* const* Sc, int pair_lim, int* best, double* ms,
                    hipStream_t st);

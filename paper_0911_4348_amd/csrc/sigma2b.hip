@@ -159,6 +159,10 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
         const int jw = njb * 16;
         const int s_jj = tid % CW, s_kk = tid / CW;
         const bool s_col = s_jj < jw && j0 + s_jj < n;
+        // per-lane partial sums of X_ij over the l-tiles, in registers where
+        // they fit beside the accumulators; otherwise every l-tile's partial is
+        // reduced over the lane groups at once and added into Xs
+        constexpr bool XREG = sizeof(T) * JB * IPW <= 56;
         T xcol[IPW][JB];
 #pragma unroll
         for (int p = 0; p < IPW; ++p)
@@ -257,18 +261,30 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                     const T* Gs = reinterpret_cast<const T*>(stage0 + buf * SB);
                     // k-steps of 4 that hold real rows (uniform across the workgroup)
                     const int nks = min(BK / 4, (n - pn * BK + 3) >> 2);
-#pragma unroll 4
-                    for (int ks = 0; ks < nks; ++ks) {
+                    // operand fragments in two register sets: the LDS reads of
+                    // k-step ks + 1 are in flight while the matrix cores work on ks
+                    T fa[2], fv[2][IPW], fb[2][NJB];
+                    auto frag = [&](int ks, int s) {
                         const int kk = ks * 4 + lg;
-                        const T av = Ab[lc * (BK + 1) + kk];
-                        T a[IPW];
+                        fa[s] = Ab[lc * (BK + 1) + kk];
 #pragma unroll
-                        for (int p = 0; p < IPW; ++p) a[p] = av * Vk[(w * IPW + p) * BK + kk];
+                        for (int p = 0; p < IPW; ++p) fv[s][p] = Vk[(w * IPW + p) * BK + kk];
 #pragma unroll
-                        for (int jb = 0; jb < NJB; ++jb) {
-                            const T bv = Gs[kk * GS_LD + jb * 16 + lc];
+                        for (int jb = 0; jb < NJB; ++jb) fb[s][jb] = Gs[kk * GS_LD + jb * 16 + lc];
+                    };
+                    frag(0, 0);
 #pragma unroll
-                            for (int p = 0; p < IPW; ++p) acc[p][jb] = Mma<T>::mma(a[p], bv, acc[p][jb]);
+                    for (int ks = 0; ks < BK / 4; ++ks) {
+                        if (ks < nks) {
+                            const int s = ks & 1;
+                            if (ks + 1 < nks) frag(ks + 1, s ^ 1);
+                            T a[IPW];
+#pragma unroll
+                            for (int p = 0; p < IPW; ++p) a[p] = fa[s] * fv[s][p];
+#pragma unroll
+                            for (int jb = 0; jb < NJB; ++jb)
+#pragma unroll
+                                for (int p = 0; p < IPW; ++p) acc[p][jb] = Mma<T>::mma(a[p], fb[s][jb], acc[p][jb]);
                         }
                     }
                 }
@@ -311,11 +327,18 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                 }
 #pragma unroll
                 for (int jb = 0; jb < NJB; ++jb) {
+                    T xc = T(0);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const T vm = Vt[Mma<T>::row(lane, r) * GS_LD + jb * 16 + lc] * acc[p][jb][r];
                         xp[r] += Gbi[rr * npj + j0 + jb * 16 + lc] * vm;
-                        xcol[p][jb] += gil[r] * vm;
+                        xc += gil[r] * vm;
+                    }
+                    if constexpr (XREG) {
+                        xcol[p][jb] += xc;
+                    } else {
+                        const T sx = sum4x16(xc);
+                        if (jb < njb && lg == 0) Xs[rr * np + j0 + jb * 16 + lc] += sx;
                     }
                 }
                 // X'_il (slice q'), partial over this chunk's columns
@@ -328,13 +351,15 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
             }
         }
         // X_ij (slice q) for this chunk's columns
+        if constexpr (XREG) {
 #pragma unroll
-        for (int p = 0; p < IPW; ++p)
+            for (int p = 0; p < IPW; ++p)
 #pragma unroll
-            for (int jb = 0; jb < JB; ++jb) {
-                const T sx = sum4x16(xcol[p][jb]);
-                if (jb < njb && lg == 0) Xs[(w * IPW + p) * np + j0 + jb * 16 + lc] = sx;
-            }
+                for (int jb = 0; jb < JB; ++jb) {
+                    const T sx = sum4x16(xcol[p][jb]);
+                    if (jb < njb && lg == 0) Xs[(w * IPW + p) * np + j0 + jb * 16 + lc] = sx;
+                }
+        }
     }
 
     // direct term D_ij = sum_l T1_il V_lj, then one store per output element
@@ -732,7 +757,7 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
 // Tile configurations the tuner chooses from: waves per workgroup (one value
 // of i each unless noted) and 16-wide column blocks per chunk.
 // 0: 8 x 208 cols, 1: 8 x 112, 2: 4 x 208, 3: 4 x 112 (single-buffered staging);
-// 4: 8 x 112, 5: 4 x 208 (double-buffered staging);
+// 4: 8 x 112, 5: 8 x 208 (double-buffered staging);
 // 6: 4 waves x 2 values of i x 112 cols, 7: 4 x 2 x 64 cols (float32 and bf16 only);
 // 8: 8 waves x 40 x 40 vector-ALU tiles, 9: 4 waves x 2 values of i x 40 x 40,
 // 10: 4 x 2 x 32 x 32 (float64 only).
@@ -808,7 +833,7 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
         case 2: return launch_cfg<MODE, 4, 13, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
         case 3: return launch_cfg<MODE, 4, 7, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
         case 4: return launch_cfg<MODE, 8, 7, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 5: return launch_cfg<MODE, 4, 13, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 5: return launch_cfg<MODE, 8, 13, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
         default:
             if constexpr (MODE == MODE_F64) {
                 const double* Vd = (const double*)V;
@@ -993,7 +1018,7 @@ int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
         case 2: return launch_batched_cfg<MODE, 4, 13, false, 1>(pl, st);
         case 3: return launch_batched_cfg<MODE, 4, 7, false, 1>(pl, st);
         case 4: return launch_batched_cfg<MODE, 8, 7, true, 1>(pl, st);
-        case 5: return launch_batched_cfg<MODE, 4, 13, true, 1>(pl, st);
+        case 5: return launch_batched_cfg<MODE, 8, 13, true, 1>(pl, st);
         default:
             if constexpr (MODE == MODE_F64) {
                 if (cfg == 8) return launch_batched_valu_cfg<8, 5, 1>(pl, st);
@@ -1011,7 +1036,7 @@ int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
 }
 
 // rows i per workgroup of a configuration
-int cfg_rows(int cfg) { return (cfg == 2 || cfg == 3 || cfg == 5) ? 4 : 8; }
+int cfg_rows(int cfg) { return (cfg == 2 || cfg == 3) ? 4 : 8; }
 
 std::string batch_key(int mode, const std::vector<int>& n) {
     std::string k = "s2bB_" + std::to_string(mode);

@@ -129,3 +129,14 @@ def test_scf_batched_requires_one_tau_grid(L):
     rc = L.negf_scf_batched(C.c_void_p(1), 2, arr, C.byref(o), None, None, None, None, None, None, None, 0, None,
                             None, None, None)
     assert rc == negf.EINVAL and b"same tau grid" in L.negf_last_error()
+
+
+def test_matrix_rate_rejects_bad_arguments(L):
+    """negf_matrix_rate validates on the host before touching a device."""
+    tf, ghz = C.c_double(), C.c_double()
+    rc = L.negf_matrix_rate(None, 0, C.byref(tf), C.byref(ghz), None)
+    assert rc == negf.EINVAL and b"ctx" in L.negf_last_error()
+    rc = L.negf_matrix_rate(C.c_void_p(1), 7, C.byref(tf), C.byref(ghz), None)
+    assert rc == negf.EINVAL and b"dtype" in L.negf_last_error()
+    rc = L.negf_matrix_rate(C.c_void_p(1), 0, None, C.byref(ghz), None)
+    assert rc == negf.EINVAL
