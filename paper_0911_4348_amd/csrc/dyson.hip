@@ -75,6 +75,8 @@ __global__ void k_sigma_tilde(int n, int sigma, const double* __restrict__ V, co
 }
 
 // ------------------------------------------------------------ FFT in LDS
+constexpr int FFT_UNR = 8;   // loads of a thread in flight at once when filling LDS
+
 __device__ __forceinline__ int bitrev(int x, int L) { return (int)(__brev((unsigned)x) >> (32 - L)); }
 
 template <class T>
@@ -108,21 +110,39 @@ __global__ __launch_bounds__(256) void k_fft_fwd(int nc, int M, int L, int CW, c
     T* br = reinterpret_cast<T*>(sm_raw);
     T* bi = br + CW * M;
     const long c0 = (long)blockIdx.x * 2 * CW;
-    for (int idx = threadIdx.x; idx < M * CW; idx += blockDim.x) {
-        const int q = idx / CW, w = idx % CW;
+    // row q = 0 holds x^_0 = (X_0 - X_M) / 2 (twist factor 1)
+    if (threadIdx.x < CW) {
+        const int w = threadIdx.x;
         const long c1 = c0 + 2 * w, c2 = c1 + 1;
-        T x1 = 0, x2 = 0;
-        if (q == 0) {
-            if (c1 < nc) x1 = T(0.5) * (X[c1] - X[(long)M * nc + c1]);
-            if (c2 < nc) x2 = T(0.5) * (X[c2] - X[(long)M * nc + c2]);
-        } else {
-            if (c1 < nc) x1 = X[(long)q * nc + c1];
-            if (c2 < nc) x2 = X[(long)q * nc + c2];
+        const T x1 = c1 < nc ? T(0.5) * (X[c1] - X[(long)M * nc + c1]) : T(0);
+        const T x2 = c2 < nc ? T(0.5) * (X[c2] - X[(long)M * nc + c2]) : T(0);
+        br[w * M] = x1;
+        bi[w * M] = x2;
+    }
+    // rows q >= 1: FFT_UNR rows of the thread's loads are in flight at once (a
+    // plain strided loop waits out one memory latency per row)
+    for (int base = CW + threadIdx.x; base < M * CW; base += FFT_UNR * blockDim.x) {
+        T x1[FFT_UNR], x2[FFT_UNR];
+#pragma unroll
+        for (int u = 0; u < FFT_UNR; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int q = idx / CW, w = idx % CW;
+            const long c1 = c0 + 2 * w, c2 = c1 + 1;
+            const bool in = idx < M * CW;
+            x1[u] = (in && c1 < nc) ? X[(long)q * nc + c1] : T(0);
+            x2[u] = (in && c2 < nc) ? X[(long)q * nc + c2] : T(0);
         }
-        const T cr = twist[2 * q], ci = twist[2 * q + 1];
-        const int r = w * M + bitrev(q, L);
-        br[r] = x1 * cr - x2 * ci;
-        bi[r] = x1 * ci + x2 * cr;
+#pragma unroll
+        for (int u = 0; u < FFT_UNR; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < M * CW) {
+                const int q = idx / CW, w = idx % CW;
+                const T cr = twist[2 * q], ci = twist[2 * q + 1];
+                const int r = w * M + bitrev(q, L);
+                br[r] = x1[u] * cr - x2[u] * ci;
+                bi[r] = x1[u] * ci + x2[u] * cr;
+            }
+        }
     }
     __syncthreads();
     fft_stages(br, bi, M, L, CW, tw);
