@@ -71,6 +71,7 @@ struct S2BBatch {
     std::vector<int> n_sorted;
     std::vector<const void*> G_sorted;
     std::vector<int*> ex_sorted;
+    std::vector<void*> gh_sorted;        // bf16 copies of the slices (bf16 mode)
     std::string key;                     // tuner cache key (mode and multiset of n_b)
 };
 int s2b_batch_prepare(negf_ctx* ctx, const char* tag, int dtype, int batch, const int* n, int n_tau,

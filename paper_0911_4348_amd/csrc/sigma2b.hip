@@ -46,6 +46,17 @@ struct Cfg {
     static constexpr int BK = MODE == MODE_BF16 ? 32 : 16;     // k-panel
 };
 
+// Per-slice data of the two low-precision modes: ex[q], the power of two every
+// slice is scaled by, and for bf16 the scaled slices themselves as bf16, rows
+// padded with zeros to ldb (a multiple of 8) elements so that a row is read in
+// 16-byte pieces. Since every slice is symmetric, row j of a slice is also the
+// k-run of column j that the B operand needs.
+struct LowP {
+    const int* ex;
+    const __bf16* gh;
+    int ldb;
+};
+
 template <int MODE, int JB>
 constexpr size_t stage_bytes() {
     typedef typename Cfg<MODE>::T T;
@@ -96,7 +107,7 @@ constexpr int waves_per_eu() {
 template <int MODE, int IB, int JB, bool DB, int IPW>
 __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, typename Cfg<MODE>::T sigma,
                                          const typename Cfg<MODE>::T* __restrict__ V,
-                                         const typename Cfg<MODE>::T* __restrict__ G, const int* __restrict__ ex,
+                                         const typename Cfg<MODE>::T* __restrict__ G, LowP lp,
                                          typename Cfg<MODE>::T* __restrict__ Sc, unsigned char* smem_raw) {
     typedef typename Cfg<MODE>::T T;
     constexpr int BK = Cfg<MODE>::BK;
@@ -137,11 +148,17 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
     const int lc = lane & 15, lg = lane >> 4;
     T sq = T(1), sqb = T(1), uq = T(1), uqb = T(1);
     if constexpr (MODE != MODE_F64) {
+        const int* ex = lp.ex;
         sq = (T)ldexpf(1.0f, ex[q]);
         sqb = (T)ldexpf(1.0f, ex[qb]);
         uq = (T)ldexpf(1.0f, -(2 * ex[q] + ex[qb]));
         uqb = (T)ldexpf(1.0f, -(ex[q] + 2 * ex[qb]));
     }
+    // bf16: the B panel comes from the bf16 copy of slice q, 16 bytes (8 values
+    // of k for one column j) per load
+    const __bf16* Ghq = MODE == MODE_BF16 ? lp.gh + (long)q * n * lp.ldb : nullptr;
+    constexpr int NV = JB * 16 * (BK / 8);                    // 16-byte pieces per B panel
+    constexpr int RBV = (NV + NT - 1) / NT;
 
     for (int e = tid; e < 3 * IR * np; e += NT) T1s[e] = T(0);     // T1s, Xs, XPs
     for (int e = tid; e < IR * npj; e += NT) {
@@ -177,12 +194,24 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
             for (int p = 0; p < IPW; ++p)
 #pragma unroll
                 for (int jb = 0; jb < NJB; ++jb) acc[p][jb] = Mma<T>::zero();
-            T rg[NSLOT], ra[RA], rv[RV];
+            T rg[MODE == MODE_BF16 ? 1 : NSLOT], ra[RA], rv[RV];
+            uint4 rgv[MODE == MODE_BF16 ? RBV : 1];
             auto load = [&](int k0) {
+                if constexpr (MODE == MODE_BF16) {
 #pragma unroll
-                for (int r = 0; r < NSLOT; ++r) {
-                    const int kk = s_kk + RP * r, k = k0 + kk;
-                    rg[r] = (s_col && kk < BK && k < n) ? Gq[(long)k * n + j0 + s_jj] : T(0);
+                    for (int r = 0; r < RBV; ++r) {
+                        const int v = tid + NT * r, jj = v / (BK / 8), k = k0 + 8 * (v % (BK / 8));
+                        const int j = j0 + jj;
+                        rgv[r] = (v < NV && jj < jw && j < n && k < lp.ldb)
+                                     ? *reinterpret_cast<const uint4*>(Ghq + (long)j * lp.ldb + k)
+                                     : uint4{0u, 0u, 0u, 0u};
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NSLOT; ++r) {
+                        const int kk = s_kk + RP * r, k = k0 + kk;
+                        rg[r] = (s_col && kk < BK && k < n) ? Gq[(long)k * n + j0 + s_jj] : T(0);
+                    }
                 }
 #pragma unroll
                 for (int r = 0; r < RA; ++r) {
@@ -199,14 +228,17 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
             };
             auto store = [&](int buf) {
                 unsigned char* sb = stage0 + buf * SB;
+                if constexpr (MODE == MODE_BF16) {
 #pragma unroll
-                for (int r = 0; r < NSLOT; ++r) {
-                    const int kk = s_kk + RP * r;
-                    if (s_jj < JB * 16 && kk < BK) {
-                        if constexpr (MODE == MODE_BF16)
-                            reinterpret_cast<__bf16*>(sb)[s_jj * BT_LD + kk] = (__bf16)(float)(rg[r] * sq);
-                        else
-                            reinterpret_cast<T*>(sb)[kk * GS_LD + s_jj] = rg[r] * sq;
+                    for (int r = 0; r < RBV; ++r) {
+                        const int v = tid + NT * r, jj = v / (BK / 8), g = v % (BK / 8);
+                        if (v < NV) *reinterpret_cast<uint4*>(reinterpret_cast<__bf16*>(sb) + jj * BT_LD + 8 * g) = rgv[r];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NSLOT; ++r) {
+                        const int kk = s_kk + RP * r;
+                        if (s_jj < JB * 16 && kk < BK) reinterpret_cast<T*>(sb)[kk * GS_LD + s_jj] = rg[r] * sq;
                     }
                 }
 #pragma unroll
@@ -617,7 +649,7 @@ __global__ __launch_bounds__(IB * 64, (IB == 8 ? 4 : (IPW > 1 ? 2 : 3))) void k_
                                                                              const double* __restrict__ V,
                                                                              const double* __restrict__ G,
                                                                              double* __restrict__ Sc) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const long lb = xcd_remap(blockIdx.x, gridDim.x);
     s2b_tile_valu<IB, TL, IPW>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, Sc, smem_raw);
 }
@@ -626,10 +658,10 @@ __global__ __launch_bounds__(IB * 64, (IB == 8 ? 4 : (IPW > 1 ? 2 : 3))) void k_
 template <int MODE, int IB, int JB, bool DB, int IPW>
 __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) void k_sigma2b(
     int n, int n_tau, int n_iblk, typename Cfg<MODE>::T sigma, const typename Cfg<MODE>::T* __restrict__ V,
-    const typename Cfg<MODE>::T* __restrict__ G, const int* __restrict__ ex, typename Cfg<MODE>::T* __restrict__ Sc) {
-    extern __shared__ unsigned char smem_raw[];
+    const typename Cfg<MODE>::T* __restrict__ G, LowP lp, typename Cfg<MODE>::T* __restrict__ Sc) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const long lb = xcd_remap(blockIdx.x, gridDim.x);
-    s2b_tile<MODE, IB, JB, DB, IPW>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, ex, Sc, smem_raw);
+    s2b_tile<MODE, IB, JB, DB, IPW>(n, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, V, G, lp, Sc, smem_raw);
 }
 
 // One system of a batch for the persistent kernel. Its work items are
@@ -639,7 +671,7 @@ struct S2BInst {
     const T* V;
     const T* G;
     T* Sc;
-    const int* ex;
+    LowP lp;
     long item0;
     T sigma;
     int n, n_iblk, n_pairs;
@@ -659,7 +691,7 @@ struct XcdCuts {
 template <int MODE, int IB, int JB, bool DB, int IPW>
 __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) void k_sigma2b_batched(
     const S2BInst<typename Cfg<MODE>::T>* __restrict__ inst, int n_inst, int n_tau, XcdCuts cuts, int* heads) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ long s_item;
     const int x = blockIdx.x & 7;       // workgroups are dealt to the XCDs round-robin
     int probe = 0;
@@ -685,7 +717,7 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) v
         const long local = it - inst[lo].item0;
         const int nib = inst[lo].n_iblk;
         s2b_tile<MODE, IB, JB, DB, IPW>(inst[lo].n, n_tau, (int)(local / nib), (int)(local % nib), inst[lo].sigma,
-                                   inst[lo].V, inst[lo].G, inst[lo].ex, inst[lo].Sc, smem_raw);
+                                   inst[lo].V, inst[lo].G, inst[lo].lp, inst[lo].Sc, smem_raw);
     }
 }
 
@@ -693,7 +725,7 @@ __global__ __launch_bounds__(IB * 64, (waves_per_eu<MODE, IB, JB, DB, IPW>())) v
 template <int IB, int TL, int IPW>
 __global__ __launch_bounds__(IB * 64, (IB == 8 ? 4 : (IPW > 1 ? 2 : 3))) void k_sigma2b_valu_batched(
     const S2BInst<double>* __restrict__ inst, int n_inst, int n_tau, XcdCuts cuts, int* heads) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ long s_item;
     const int x = blockIdx.x & 7;
     int probe = 0;
@@ -754,6 +786,39 @@ __global__ __launch_bounds__(256) void k_slice_exponent(int n, const float* __re
     }
 }
 
+// gh[q][j][k] = bf16(G_q[j][k] 2^ex[q]) for k < n, 0 for n <= k < ldb; one
+// 16-byte piece (8 values of k) per thread, grid (pieces / 256, n_tau)
+__global__ __launch_bounds__(256) void k_slice_bf16(int n, int ldb, const float* __restrict__ G,
+                                                    const int* __restrict__ ex, __bf16* __restrict__ gh) {
+    const int q = blockIdx.y;
+    const int per_row = ldb / 8;
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v >= (long)n * per_row) return;
+    const int j = (int)(v / per_row), k0 = 8 * (int)(v % per_row);
+    const float sc = ldexpf(1.0f, ex[q]);
+    const float* g = G + (long)q * n * n + (long)j * n;
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = (__bf16)(k0 + e < n ? g[k0 + e] * sc : 0.0f);
+    *reinterpret_cast<bf16x8*>(gh + ((long)q * n + j) * ldb + k0) = out;
+}
+
+int bf16_ldb(int n) { return (n + 7) & ~7; }
+
+// The bf16 copy of every slice (after k_slice_exponent has filled ex).
+int slices_to_bf16(int n, int n_tau, const float* G, const int* ex, __bf16* gh, hipStream_t st) {
+    const long pieces = (long)n * (bf16_ldb(n) / 8);
+    const long gx = (pieces + 255) / 256;
+    if (gx > 0x7fffffffL || n_tau > 65535) {
+        set_error("Sigma-2B bf16 staging: %d slices of n_b = %d exceed the launch limits", n_tau, n);
+        return NEGF_EINVAL;
+    }
+    hipLaunchKernelGGL(k_slice_bf16, dim3((unsigned)gx, (unsigned)n_tau), dim3(256), 0, st, n, bf16_ldb(n), G, ex,
+                       gh);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+
 // Tile configurations the tuner chooses from: waves per workgroup (one value
 // of i each unless noted) and 16-wide column blocks per chunk.
 // 0: 8 x 208 cols, 1: 8 x 112, 2: 4 x 208, 3: 4 x 112 (single-buffered staging);
@@ -791,7 +856,7 @@ int launch_valu_cfg(int n, int n_tau, int sigma, const double* V, const double* 
 
 template <int MODE, int IB, int JB, bool DB, int IPW>
 int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, const typename Cfg<MODE>::T* G,
-               const int* ex, typename Cfg<MODE>::T* Sc, hipStream_t st) {
+               LowP lp, typename Cfg<MODE>::T* Sc, hipStream_t st) {
     typedef typename Cfg<MODE>::T T;
     const int n_pairs = (n_tau + 1) / 2;
     const int n_iblk = (n + IB * IPW - 1) / (IB * IPW);
@@ -813,7 +878,7 @@ int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, cons
         attr_set = true;
     }
     hipLaunchKernelGGL((k_sigma2b<MODE, IB, JB, DB, IPW>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, n_tau, n_iblk,
-                       T(sigma), V, G, ex, Sc);
+                       T(sigma), V, G, lp, Sc);
     LAUNCH_CHECK();
     return NEGF_OK;
 }
@@ -822,18 +887,27 @@ template <int MODE>
 int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V,
            const typename Cfg<MODE>::T* G, typename Cfg<MODE>::T* Sc, int cfg, hipStream_t st) {
     int* ex = nullptr;
+    LowP lp{nullptr, nullptr, 0};
     if (MODE != MODE_F64) {
         NEGF_TRY(scratch_t(ctx, "s2b_ex", n_tau, &ex));
         hipLaunchKernelGGL(k_slice_exponent, dim3(n_tau), dim3(256), 0, st, n, (const float*)G, ex);
         LAUNCH_CHECK();
+        lp.ex = ex;
+    }
+    if (MODE == MODE_BF16) {
+        __bf16* gh = nullptr;
+        NEGF_TRY(scratch_t(ctx, "s2b_gh", (size_t)n_tau * n * bf16_ldb(n), &gh));
+        NEGF_TRY(slices_to_bf16(n, n_tau, (const float*)G, ex, gh, st));
+        lp.gh = gh;
+        lp.ldb = bf16_ldb(n);
     }
     switch (cfg) {
-        case 0: return launch_cfg<MODE, 8, 13, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 1: return launch_cfg<MODE, 8, 7, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 2: return launch_cfg<MODE, 4, 13, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 3: return launch_cfg<MODE, 4, 7, false, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 4: return launch_cfg<MODE, 8, 7, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
-        case 5: return launch_cfg<MODE, 8, 13, true, 1>(n, n_tau, sigma, V, G, ex, Sc, st);
+        case 0: return launch_cfg<MODE, 8, 13, false, 1>(n, n_tau, sigma, V, G, lp, Sc, st);
+        case 1: return launch_cfg<MODE, 8, 7, false, 1>(n, n_tau, sigma, V, G, lp, Sc, st);
+        case 2: return launch_cfg<MODE, 4, 13, false, 1>(n, n_tau, sigma, V, G, lp, Sc, st);
+        case 3: return launch_cfg<MODE, 4, 7, false, 1>(n, n_tau, sigma, V, G, lp, Sc, st);
+        case 4: return launch_cfg<MODE, 8, 7, true, 1>(n, n_tau, sigma, V, G, lp, Sc, st);
+        case 5: return launch_cfg<MODE, 8, 13, true, 1>(n, n_tau, sigma, V, G, lp, Sc, st);
         default:
             if constexpr (MODE == MODE_F64) {
                 const double* Vd = (const double*)V;
@@ -845,8 +919,8 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
                 set_error("tile configuration %d is for float32 and bf16 only", cfg);
                 return NEGF_EINVAL;
             } else {
-                if (cfg == 6) return launch_cfg<MODE, 4, 7, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
-                if (cfg == 7) return launch_cfg<MODE, 4, 4, false, 2>(n, n_tau, sigma, V, G, ex, Sc, st);
+                if (cfg == 6) return launch_cfg<MODE, 4, 7, false, 2>(n, n_tau, sigma, V, G, lp, Sc, st);
+                if (cfg == 7) return launch_cfg<MODE, 4, 4, false, 2>(n, n_tau, sigma, V, G, lp, Sc, st);
                 set_error("tile configuration %d is for float64 only", cfg);
                 return NEGF_EINVAL;
             }
@@ -1059,11 +1133,19 @@ int prepare_typed(negf_ctx* ctx, const std::string& tag, int batch, const int* n
     std::vector<double> cost(batch);
     int* ex = nullptr;
     if (pl->mode != MODE_F64) NEGF_TRY(scratch_t(ctx, ("s2bB_ex_" + tag).c_str(), (size_t)batch * n_tau, &ex));
+    __bf16* gh = nullptr;
+    if (pl->mode == MODE_BF16) {
+        size_t tot = 0;
+        for (int b = 0; b < batch; ++b) tot += (size_t)n_tau * n[b] * bf16_ldb(n[b]);
+        NEGF_TRY(scratch_t(ctx, ("s2bB_gh_" + tag).c_str(), tot, &gh));
+    }
+    size_t gh_off = 0;
     long items = 0;
     double total = 0.0;
     pl->n_sorted.assign(batch, 0);
     pl->G_sorted.assign(batch, nullptr);
     pl->ex_sorted.assign(batch, nullptr);
+    pl->gh_sorted.assign(batch, nullptr);
     pl->max_n = 0;
     for (int r = 0; r < batch; ++r) {
         const int b = order[r];
@@ -1071,7 +1153,11 @@ int prepare_typed(negf_ctx* ctx, const std::string& tag, int batch, const int* n
         I.V = (const T*)V[b];
         I.G = (const T*)G[b];
         I.Sc = (T*)Sc[b];
-        I.ex = ex ? ex + (long)r * n_tau : nullptr;
+        I.lp.ex = ex ? ex + (long)r * n_tau : nullptr;
+        I.lp.gh = gh ? gh + gh_off : nullptr;
+        I.lp.ldb = gh ? bf16_ldb(n[b]) : 0;
+        pl->gh_sorted[r] = gh ? gh + gh_off : nullptr;
+        if (gh) gh_off += (size_t)n_tau * n[b] * bf16_ldb(n[b]);
         I.item0 = items;
         I.sigma = (T)sigma[b];
         I.n = n[b];
@@ -1141,6 +1227,9 @@ int s2b_batch_launch(const S2BBatch& pl, hipStream_t st) {
             hipLaunchKernelGGL(k_slice_exponent, dim3(pl.n_tau), dim3(256), 0, st, pl.n_sorted[r],
                                (const float*)pl.G_sorted[r], pl.ex_sorted[r]);
             LAUNCH_CHECK();
+            if (pl.mode == MODE_BF16)
+                NEGF_TRY(slices_to_bf16(pl.n_sorted[r], pl.n_tau, (const float*)pl.G_sorted[r], pl.ex_sorted[r],
+                                        (__bf16*)pl.gh_sorted[r], st));
         }
     }
     if (pl.mode == MODE_F64) return launch_batched<MODE_F64>(pl, pl.cfg, st);
