@@ -36,9 +36,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "f227d761d053d3a8"
-TRAFFIC_F64_NB199 = {0: 656744793, 1: 657080344, 2: 656802977, 3: 658109172, 4: 657756080, 5: 1166288718,
-                     8: 663916869, 9: 664902965, 10: 663901757}
+TRAFFIC_SRC_SHA256 = "017afd1364f9568d"
+TRAFFIC_F64_NB199 = {0: 656740176, 1: 657091234, 2: 656804856, 3: 658118996, 4: 657750719, 5: 1166569591,
+                     8: 663843489, 9: 665013886, 10: 663763583}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):
