@@ -270,8 +270,10 @@ int negf_dyson_step(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma
                     double alpha, int symmetrize, int conv_algo, int dtype, void* G_out,
                     double* E_out, double* N_out, void* stream);
 
-/* Galitskii-Migdal energy and particle number of (G, Sigma_c) alone (float64
- * accumulation), the same formulas as in negf_dyson_step. Synchronises. */
+/* Galitskii-Migdal energy and particle number of (G, Sigma_c) alone, the same
+ * formulas as in negf_dyson_step (paper Sec. 2.3): float64 products and
+ * compensated (Neumaier) float64 sums in a fixed order, in every dtype.
+ * Synchronises. */
 int negf_energy(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma,
                 const double* h, const double* V, const void* G, const void* Sigma_c,
                 int dtype, double* E_out, double* N_out, void* stream);

@@ -41,21 +41,50 @@ inline unsigned grid_for(long total) {
     return (unsigned)b;
 }
 
+// Compensated (Neumaier) float64 sum: the value is s + c, where c gathers the
+// rounding error of every addition into s (exact for each addition, since the
+// error of a rounded sum of two doubles is itself a double). Merging two such
+// sums adds the partner's s the same way and its c plainly; the merge is
+// symmetric, so every lane of a butterfly ends with the same pair.
+struct CSum {
+    double s, c;
+    __device__ void add(double x) {
+#pragma clang fp contract(off)
+        const double t = s + x;
+        c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    __device__ void merge(double os, double oc) {
+        add(os);
+        c += oc;
+    }
+    __device__ double value() const { return s + c; }
+};
+
+// Block-wide compensated sum, in a fixed order (waves by butterfly, then the
+// waves' partial sums in wave order by thread 0). red holds 2 (NT/64) + 2 doubles.
 template <int NT>
-__device__ double block_sum_d(double v, double* red) {
-    v = wave_sum(v);
+__device__ double block_csum(CSum v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double os = __shfl_xor(v.s, off, 64), oc = __shfl_xor(v.c, off, 64);
+        v.merge(os, oc);
+    }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < NT / 64; ++k) s += red[k];
-        red[NT / 64] = s;
+    if (lane == 0) {
+        red[2 * w] = v.s;
+        red[2 * w + 1] = v.c;
     }
     __syncthreads();
-    return red[NT / 64];
+    if (threadIdx.x == 0) {
+        CSum t{red[0], red[1]};
+        for (int k = 1; k < NT / 64; ++k) t.merge(red[2 * k], red[2 * k + 1]);
+        red[2 * (NT / 64)] = t.value();
+    }
+    __syncthreads();
+    return red[2 * (NT / 64)];
 }
+
 
 // ------------------------------------------------------------ St = Sigma^HF[-G_M] - Sigma0
 template <class T>
@@ -536,21 +565,22 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, T* G) {
 }
 
 // ------------------------------------------------------------ energy
+// part[q] = Tr[Sc(beta - tau_q) G(tau_q)], float64 products, compensated sum
 template <class T>
 __global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T* __restrict__ Sc,
                                                        const T* __restrict__ G, double* part) {
-    __shared__ double red[256 / 64 + 1];
+    __shared__ double red[2 * (256 / 64) + 2];
     const int q = blockIdx.x;
     const long nn = (long)n * n;
     const T* S = Sc + (long)(n_tau - 1 - q) * nn;
     const T* g = G + (long)q * nn;
-    double s = 0.0;
+    CSum s{0.0, 0.0};
     for (long e = threadIdx.x; e < nn; e += 256) {
         const int i = (int)(e / n), j = (int)(e % n);
-        s += (double)S[e] * (double)g[(long)j * n + i];
+        s.add((double)S[e] * (double)g[(long)j * n + i]);
     }
-    s = block_sum_d<256>(s, red);
-    if (threadIdx.x == 0) part[q] = s;
+    const double tot = block_csum<256>(s, red);
+    if (threadIdx.x == 0) part[q] = tot;
 }
 
 template <class T>
@@ -558,23 +588,24 @@ __global__ __launch_bounds__(256) void k_energy_final(int n, int n_tau, int sigm
                                                       const double* __restrict__ V, const T* __restrict__ GM,
                                                       const double* __restrict__ w, const double* __restrict__ part,
                                                       double* out) {
-    __shared__ double red[256 / 64 + 1];
-    double ec = 0.0;
-    for (int q = threadIdx.x; q < n_tau; q += 256) ec += w[q] * part[q];
-    ec = block_sum_d<256>(ec, red);
+    __shared__ double red[2 * (256 / 64) + 2];
+    CSum cec{0.0, 0.0};
+    for (int q = threadIdx.x; q < n_tau; q += 256) cec.add(w[q] * part[q]);
+    const double ec = block_csum<256>(cec, red);
     const long nn = (long)n * n;
-    double e1 = 0.0, e2 = 0.0, tr = 0.0;
+    CSum c1{0.0, 0.0}, c2{0.0, 0.0}, ctr{0.0, 0.0};
     for (long e = threadIdx.x; e < nn; e += 256) {
         const int i = (int)(e / n), j = (int)(e % n);
         const double rij = -(double)GM[e], rji = -(double)GM[(long)j * n + i];
         const double rii = -(double)GM[(long)i * n + i], rjj = -(double)GM[(long)j * n + j];
-        e1 += h[e] * rji;
-        e2 += sigma * rii * V[e] * rjj - V[e] * rij * rji;
-        if (i == j) tr += rii;
+        c1.add(h[e] * rji);
+        c2.add(sigma * rii * V[e] * rjj);
+        c2.add(-(V[e] * rij * rji));
+        if (i == j) ctr.add(rii);
     }
-    e1 = block_sum_d<256>(e1, red);
-    e2 = block_sum_d<256>(e2, red);
-    tr = block_sum_d<256>(tr, red);
+    const double e1 = block_csum<256>(c1, red);
+    const double e2 = block_csum<256>(c2, red);
+    const double tr = block_csum<256>(ctr, red);
     if (threadIdx.x == 0) {
         out[0] = sigma * (e1 + 0.5 * e2) - 0.5 * sigma * ec;
         out[1] = sigma * tr;
