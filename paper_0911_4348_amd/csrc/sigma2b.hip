@@ -87,6 +87,26 @@ __device__ __forceinline__ long xcd_remap(long b, long nb) {
     return x * base + (x < rem ? x : rem) + k;
 }
 
+// Global-to-LDS copy of COUNT elements by NT threads with all of a thread's
+// loads in flight before the first store (a strided copy loop waits out one
+// memory latency per element). ld(e) returns element e, bounds included;
+// st(e, v) writes it.
+template <class T, int COUNT, int NT, class Ld, class St>
+__device__ __forceinline__ void copy_all(int tid, Ld ld, St st) {
+    constexpr int R = (COUNT + NT - 1) / NT;
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = tid + NT * r;
+        v[r] = (COUNT % NT == 0 || e < COUNT) ? ld(e) : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = tid + NT * r;
+        if (COUNT % NT == 0 || e < COUNT) st(e, v[r]);
+    }
+}
+
 // minimum waves per SIMD the register allocation must allow for a configuration
 template <int MODE, int IB, int JB, bool DB, int IPW>
 constexpr int waves_per_eu() {
@@ -339,11 +359,25 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                                 if (Mma<T>::row(lane, r) == lc) T1s[(w * IPW + p) * np + l0 + lc] = acc[p][jb][r];
                     }
             }
-            // V rows l0..l0+15 (this chunk's columns, zero-padded) into buffer 0
-            for (int e = tid; e < 16 * JB * 16; e += NT) {
-                const int ll = e / (JB * 16), jj = e - ll * (JB * 16);
-                const int l = l0 + ll, j = j0 + jj;
-                Vt[ll * GS_LD + jj] = (l < n && jj < jw && j < n) ? V[(long)l * n + j] : T(0);
+            // V rows l0..l0+15 (this chunk's columns, zero-padded) into buffer 0;
+            // float32 storage has the registers to keep all of a thread's loads
+            // in flight (float64 copies element by element: its accumulators
+            // leave no room)
+            {
+                auto ld = [&](int e) {
+                    const int ll = e / (JB * 16), jj = e - ll * (JB * 16);
+                    const int l = l0 + ll, j = j0 + jj;
+                    return (l < n && jj < jw && j < n) ? V[(long)l * n + j] : T(0);
+                };
+                auto st = [&](int e, T v) {
+                    const int ll = e / (JB * 16), jj = e - ll * (JB * 16);
+                    Vt[ll * GS_LD + jj] = v;
+                };
+                if constexpr (MODE == MODE_F64) {
+                    for (int e = tid; e < 16 * JB * 16; e += NT) st(e, ld(e));
+                } else {
+                    copy_all<T, 16 * JB * 16, NT>(tid, ld, st);
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -404,11 +438,30 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
 #pragma unroll
             for (int m = 0; m < DM; ++m) d[p][m] = T(0);
         for (int l0 = 0; l0 < n; l0 += 16) {
-            __syncthreads();
-            for (int e = tid; e < 16 * jw; e += NT) {
-                const int ll = e / jw, jj = e - ll * jw;
-                const int l = l0 + ll, j = j0 + jj;
-                Vt[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
+            if constexpr (MODE == MODE_F64) {
+                __syncthreads();
+                for (int e = tid; e < 16 * jw; e += NT) {
+                    const int ll = e / jw, jj = e - ll * jw;
+                    const int l = l0 + ll, j = j0 + jj;
+                    Vt[ll * GS_LD + jj] = (l < n && j < n) ? V[(long)l * n + j] : T(0);
+                }
+            } else {
+                // all loads in flight, then the barrier that lets the stores
+                // replace the tile the previous l-step read
+                constexpr int R = (16 * JB * 16 + NT - 1) / NT;
+                T v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int e = tid + NT * r, ll = e / (JB * 16), jj = e - ll * (JB * 16);
+                    const int l = l0 + ll, j = j0 + jj;
+                    v[r] = (e < 16 * JB * 16 && l < n && jj < jw && j < n) ? V[(long)l * n + j] : T(0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int e = tid + NT * r, ll = e / (JB * 16), jj = e - ll * (JB * 16);
+                    if (e < 16 * JB * 16) Vt[ll * GS_LD + jj] = v[r];
+                }
             }
             __syncthreads();
             for (int ll = 0; ll < 16; ++ll) {
