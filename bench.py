@@ -248,8 +248,8 @@ def main():
                          "(reads BYTES, writes BYTES) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the method's data-parallel hot path runs on a single "
-              "MI355X in this build (multi-GPU sharding is described, not run).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the hot path on a single MI355X "
+              "and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
 
     import torch
