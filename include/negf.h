@@ -169,10 +169,12 @@ int negf_g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau, double b
  * V (dev, float64 for NEGF_F64, float32 otherwise) [n_b*n_b], symmetric.
  * G (dev) [n_tau][n_b][n_b], every slice symmetric; Sigma_c (dev, same shape);
  * G and Sigma_c are float64 for NEGF_F64 and float32 for NEGF_F32 / NEGF_BF16.
- * For NEGF_BF16 each slice is scaled by a power of two before rounding to
- * bf16 and the result unscaled, so no slice underflows before the output.
- * Sigma_c must not alias G. Errors: NEGF_EINVAL (n_b < 1, n_tau < 2, sigma
- * not 1 or 2, bad dtype, NULL pointers). */
+ * For NEGF_F32 and NEGF_BF16 each slice is scaled by a power of two (so its
+ * largest entry lies in [1/2, 1)) and the result unscaled, so no slice
+ * underflows before the output. NEGF_BF16 keeps a bf16 copy of the scaled
+ * slices in context scratch (n_tau * n_b * 8*ceil(n_b/8) * 2 bytes), written
+ * once per call. Sigma_c must not alias G. Errors: NEGF_EINVAL (n_b < 1,
+ * n_tau < 2, sigma not 1 or 2, bad dtype, NULL pointers). */
 int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
                  const void* G, void* Sigma_c, int dtype, void* stream);
 
