@@ -124,6 +124,19 @@ def test_sigma2b_low_precision(ctx, torch_mod, dtype, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("dtype,tol", [("f32", 3e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("n,n_tau", [(1, 3), (2, 2), (3, 5), (8, 4), (15, 3), (17, 6)])
+def test_sigma2b_low_precision_edge_sizes(ctx, torch_mod, dtype, tol, n, n_tau):
+    """Sizes below and around one 16-wide block and one 8-wide bf16 row piece
+    (the bf16 copy pads rows to 8), with and without a middle slice."""
+    V = _pos_V(n, 21)
+    G = W.random_symmetric_slices(n, n_tau, 22)
+    ref = S.sigma2b(V, G, 2)
+    f32 = torch_mod.float32
+    out = negf.sigma2b(ctx, dev(torch_mod, V, f32), dev(torch_mod, G, f32), 2, dtype=dtype)
+    assert relerr(host(out), ref) < tol, (n, n_tau)
+
+
 def test_sigma2b_microbench_sampled(ctx, torch_mod):
     """Full 199-function / 1025-slice microbenchmark input; oracle on sampled slices."""
     s = W.config_sigma_bench()
