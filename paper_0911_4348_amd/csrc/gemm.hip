@@ -4,7 +4,8 @@
 //
 // Workgroup tile 64 x 64, k-panel 16, four waves each owning a 32 x 32
 // quadrant (2 x 2 MFMA tiles). Panels are staged in LDS k-major so that each
-// lane's operand fetch for one MFMA is a row of 16 consecutive elements.
+// lane's operand fetch for one MFMA is a row of 16 consecutive elements, in two
+// buffers (the next panel is loaded while the current one is multiplied).
 #include "common.h"
 #include "mfma.h"
 
@@ -13,18 +14,32 @@ namespace {
 
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16, GB_PAD = 2;
 
+// Workgroups are dealt to the 8 XCDs round-robin by linear index; renumber them
+// so that each XCD receives a contiguous range of logical blocks, which puts
+// all tiles of one matrix of the batch on one XCD (its operands are then read
+// from HBM once into that XCD's L2, not once per XCD).
+__device__ __forceinline__ long gemm_xcd_remap(long b, long nb) {
+    const long x = b & 7, k = b >> 3;
+    const long base = nb >> 3, rem = nb & 7;
+    return x * base + (x < rem ? x : rem) + k;
+}
+
 template <class T, bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, const T* __restrict__ A,
                                               long lda, long sA, const T* __restrict__ B, long ldb,
                                               long sB, T beta, const T* Cin, long ldci, long sCi,
                                               T* C, long ldc, long sC, const T* __restrict__ S,
                                               long sS) {
-    __shared__ T As[GB_K][GB_M + GB_PAD];
-    __shared__ T Bs[GB_K][GB_N + GB_PAD];
+    // two LDS buffers: the loads of k-panel p + 1 are in flight while the
+    // matrix cores work on panel p, and one barrier per panel remains
+    __shared__ T As[2][GB_K][GB_M + GB_PAD];
+    __shared__ T Bs[2][GB_K][GB_N + GB_PAD];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
-    const long b = blockIdx.z;
-    const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+    const long nbx = gridDim.x, nby = gridDim.y;
+    const long lb = gemm_xcd_remap(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z), nbx * nby * gridDim.z);
+    const long b = lb / (nbx * nby);
+    const int m0 = (int)((lb / nbx) % nby) * GB_M, n0 = (int)(lb % nbx) * GB_N;
     A += b * sA;
     B += b * sB;
     if (S) S += b * sS;
@@ -32,8 +47,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = Mma<T>::zero();
 
-    for (int k0 = 0; k0 < K; k0 += GB_K) {
-        T ra[4], rb[4];
+    T ra[4], rb[4];
+    auto load = [&](int k0) {
         // A panel: op(A)(m, k) for m in [m0, m0+64), k in [k0, k0+16)
         if (!TA) {
             const int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
@@ -63,30 +78,40 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
                 rb[e] = (n < N && k < K) ? B[(long)n * ldb + k] : T(0);
             }
         }
-        __syncthreads();
+    };
+    auto store = [&](int buf) {
         if (!TA) {
-            for (int e = 0; e < 4; ++e) As[(tid & 3) * 4 + e][tid >> 2] = ra[e];
+            for (int e = 0; e < 4; ++e) As[buf][(tid & 3) * 4 + e][tid >> 2] = ra[e];
         } else {
-            for (int e = 0; e < 4; ++e) As[tid >> 4][(tid & 15) * 4 + e] = ra[e];
+            for (int e = 0; e < 4; ++e) As[buf][tid >> 4][(tid & 15) * 4 + e] = ra[e];
         }
         if (!TB) {
-            for (int e = 0; e < 4; ++e) Bs[tid >> 4][(tid & 15) * 4 + e] = rb[e];
+            for (int e = 0; e < 4; ++e) Bs[buf][tid >> 4][(tid & 15) * 4 + e] = rb[e];
         } else {
-            for (int e = 0; e < 4; ++e) Bs[(tid & 3) * 4 + e][tid >> 2] = rb[e];
+            for (int e = 0; e < 4; ++e) Bs[buf][(tid & 3) * 4 + e][tid >> 2] = rb[e];
         }
-        __syncthreads();
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int k0 = 0, buf = 0; k0 < K; k0 += GB_K, buf ^= 1) {
+        const bool more = k0 + GB_K < K;
+        if (more) load(k0 + GB_K);
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            T a0 = As[kk][wr * 32 + (lane & 15)];
-            T a1 = As[kk][wr * 32 + 16 + (lane & 15)];
-            T b0 = Bs[kk][wc * 32 + (lane & 15)];
-            T b1 = Bs[kk][wc * 32 + 16 + (lane & 15)];
+            T a0 = As[buf][kk][wr * 32 + (lane & 15)];
+            T a1 = As[buf][kk][wr * 32 + 16 + (lane & 15)];
+            T b0 = Bs[buf][kk][wc * 32 + (lane & 15)];
+            T b1 = Bs[buf][kk][wc * 32 + 16 + (lane & 15)];
             acc[0][0] = Mma<T>::mma(a0, b0, acc[0][0]);
             acc[0][1] = Mma<T>::mma(a0, b1, acc[0][1]);
             acc[1][0] = Mma<T>::mma(a1, b0, acc[1][0]);
             acc[1][1] = Mma<T>::mma(a1, b1, acc[1][1]);
         }
+        // the other buffer was last read before the previous barrier
+        if (more) store(buf ^ 1);
+        __syncthreads();
     }
     C += b * sC;
     if (Cin) Cin += b * sCi;
