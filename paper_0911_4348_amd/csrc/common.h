@@ -58,6 +58,11 @@ int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha,
          const T* A, long lda, long sA, const T* B, long ldb, long sB,
          T beta, const T* Cin, long ldci, long sCi, T* C, long ldc, long sC,
          int batch, const T* colscale = nullptr, long sS = 0);
+// Batched complex product of n x n matrices in planar form: Cr + i Ci =
+// (Ar + i Ai)(Br + i Bi), matrix b of each array at offset b * stride.
+template <class T>
+int cgemm(hipStream_t st, int n, const T* Ar, const T* Ai, const T* Br, const T* Bi, T* Cr, T* Ci, long stride,
+          int batch);
 
 // ---------------------------------------------------------------- HF pieces
 // Work list of the persistent Sigma-2B kernel for a batch of systems.

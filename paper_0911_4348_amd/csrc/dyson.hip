@@ -738,10 +738,7 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
         NEGF_TRY(fft_launch<T>(false, (int)nn, M, G_in, nullptr, Bre, Bim, twist, tw, st));
         hipLaunchKernelGGL((k_freq_prep<T>), dim3(grid_for(nn * nk)), dim3(256), 0, st, nn, nk, (T)dtau, St, Are, Aim);
         LAUNCH_CHECK();
-        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Are, n, nn, Bre, n, nn, T(0), nullptr, 0, 0, Cre, n, nn, nk));
-        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(-1), Aim, n, nn, Bim, n, nn, T(1), Cre, n, nn, Cre, n, nn, nk));
-        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Are, n, nn, Bim, n, nn, T(0), nullptr, 0, 0, Cim, n, nn, nk));
-        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Aim, n, nn, Bre, n, nn, T(1), Cim, n, nn, Cim, n, nn, nk));
+        NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk));
         NEGF_TRY(fft_launch<T>(true, (int)nn, M, Cre, Cim, I1, nullptr, twist, tw, st));
         // end points p = 0 and p = M
         T *Lm, *Rm, *Em, *SR;

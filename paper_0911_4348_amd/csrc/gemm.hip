@@ -128,7 +128,120 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
             }
 }
 
+// Batched complex product C = A B of n x n matrices in planar form (real and
+// imaginary parts in separate arrays, matrix b at offset b * stride):
+//   Cr = Ar Br - Ai Bi,  Ci = Ar Bi + Ai Br,
+// each part accumulated in one chain over k. The tile layout, staging and
+// XCD order are those of k_gemm; every operand tile is read once for both
+// parts (four real products would read each operand twice and write, reread
+// and rewrite the outputs).
+template <class T>
+__global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, const T* __restrict__ Ai,
+                                               const T* __restrict__ Br, const T* __restrict__ Bi,
+                                               T* __restrict__ Cr, T* __restrict__ Ci, long stride) {
+    __shared__ T Asr[2][GB_K][GB_M + GB_PAD], Asi[2][GB_K][GB_M + GB_PAD];
+    __shared__ T Bsr[2][GB_K][GB_N + GB_PAD], Bsi[2][GB_K][GB_N + GB_PAD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const long nbx = gridDim.x, nby = gridDim.y;
+    const long lb = gemm_xcd_remap(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z), nbx * nby * gridDim.z);
+    const long b = lb / (nbx * nby);
+    const int m0 = (int)((lb / nbx) % nby) * GB_M, n0 = (int)(lb % nbx) * GB_N;
+    const long off = b * stride;
+    typename Mma<T>::acc_t cr[2][2], ci[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) cr[i][j] = ci[i][j] = Mma<T>::zero();
+    T rar[4], rai[4], rbr[4], rbi[4];
+    auto load = [&](int k0) {
+        {
+            const int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
+            for (int e = 0; e < 4; ++e) {
+                const int k = kb + e;
+                const bool in = m < n && k < n;
+                rar[e] = in ? Ar[off + (long)m * n + k] : T(0);
+                rai[e] = in ? Ai[off + (long)m * n + k] : T(0);
+            }
+        }
+        {
+            const int k = k0 + (tid >> 4), nb = n0 + (tid & 15) * 4;
+            for (int e = 0; e < 4; ++e) {
+                const int c = nb + e;
+                const bool in = c < n && k < n;
+                rbr[e] = in ? Br[off + (long)k * n + c] : T(0);
+                rbi[e] = in ? Bi[off + (long)k * n + c] : T(0);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+        for (int e = 0; e < 4; ++e) {
+            Asr[buf][(tid & 3) * 4 + e][tid >> 2] = rar[e];
+            Asi[buf][(tid & 3) * 4 + e][tid >> 2] = rai[e];
+            Bsr[buf][tid >> 4][(tid & 15) * 4 + e] = rbr[e];
+            Bsi[buf][tid >> 4][(tid & 15) * 4 + e] = rbi[e];
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int k0 = 0, buf = 0; k0 < n; k0 += GB_K, buf ^= 1) {
+        const bool more = k0 + GB_K < n;
+        if (more) load(k0 + GB_K);
+#pragma unroll
+        for (int ks = 0; ks < GB_K / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                ar[h] = Asr[buf][kk][wr * 32 + 16 * h + (lane & 15)];
+                ai[h] = Asi[buf][kk][wr * 32 + 16 * h + (lane & 15)];
+                br[h] = Bsr[buf][kk][wc * 32 + 16 * h + (lane & 15)];
+                bi[h] = Bsi[buf][kk][wc * 32 + 16 * h + (lane & 15)];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = Mma<T>::mma(ar[i], br[j], cr[i][j]);
+                    cr[i][j] = Mma<T>::mma(-ai[i], bi[j], cr[i][j]);
+                    ci[i][j] = Mma<T>::mma(ar[i], bi[j], ci[i][j]);
+                    ci[i][j] = Mma<T>::mma(ai[i], br[j], ci[i][j]);
+                }
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+    for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr * 32 + mi * 16 + Mma<T>::row(lane, r);
+                const int col = n0 + wc * 32 + ni * 16 + (lane & 15);
+                if (row < n && col < n) {
+                    Cr[off + (long)row * n + col] = cr[mi][ni][r];
+                    Ci[off + (long)row * n + col] = ci[mi][ni][r];
+                }
+            }
+}
+
 }  // namespace
+
+template <class T>
+int cgemm(hipStream_t st, int n, const T* Ar, const T* Ai, const T* Br, const T* Bi, T* Cr, T* Ci, long stride,
+          int batch) {
+    if (n <= 0 || batch <= 0) return NEGF_OK;
+    for (int b0 = 0; b0 < batch; b0 += 65535) {
+        const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+        const long o = (long)b0 * stride;
+        dim3 grid((n + GB_N - 1) / GB_N, (n + GB_M - 1) / GB_M, nb);
+        hipLaunchKernelGGL((k_cgemm<T>), grid, dim3(256), 0, st, n, Ar + o, Ai + o, Br + o, Bi + o, Cr + o, Ci + o,
+                           stride);
+        LAUNCH_CHECK();
+    }
+    return NEGF_OK;
+}
+template int cgemm<double>(hipStream_t, int, const double*, const double*, const double*, const double*, double*,
+                           double*, long, int);
+template int cgemm<float>(hipStream_t, int, const float*, const float*, const float*, const float*, float*, float*,
+                          long, int);
 
 template <class T>
 int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha, const T* A, long lda,
