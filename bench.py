@@ -36,7 +36,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "a8b96e8fc69339ba"
+TRAFFIC_SRC_SHA256 = "7d2c805646dd4f94"
 TRAFFIC_F64_NB199 = {0: 656742590, 1: 656969179, 2: 656790252, 3: 657682137, 4: 657391888, 5: 1165370103,
                      8: 660867600, 9: 663135249, 10: 662119021}
 

@@ -110,7 +110,9 @@ __device__ __forceinline__ void copy_all(int tid, Ld ld, St st) {
 // minimum waves per SIMD the register allocation must allow for a configuration
 template <int MODE, int IB, int JB, bool DB, int IPW>
 constexpr int waves_per_eu() {
-    // chosen so that every configuration compiles without register spills
+    // the highest occupancy at which a configuration spills few or no
+    // registers (the float64 double-buffered 208-column tile and some float32
+    // tiles at four waves per SIMD still spill a little)
     if (IPW > 1) return JB > 4 ? 2 : 3;
     if (MODE == MODE_F64) return JB > 8 ? (IB == 4 ? 1 : 2) : 2;
     if (MODE == MODE_BF16) return JB > 8 ? (IB == 4 ? 1 : 2) : (DB ? 2 : (IB == 4 ? 2 : 4));
@@ -118,9 +120,13 @@ constexpr int waves_per_eu() {
 }
 
 // The k-panels of G (B operand), Gb (A operand rows) and V_i (A operand scale)
-// are double-buffered: while the matrix cores work on panel p from LDS, the
-// loads of panel p+1 are in flight into registers, then written to the other
-// LDS buffer; one barrier per panel.
+// are staged through LDS. With DB they are double-buffered: while the matrix
+// cores work on panel p, the loads of panel p+1 are in flight into registers,
+// then written to the other LDS buffer (one barrier per panel). Without DB a
+// panel is loaded, stored and multiplied in turn (two barriers per panel).
+// Inside a panel the operand fragments of k-step s+1 are read from LDS while
+// the matrix cores work on step s. In bf16 the B panel is copied from the bf16
+// slices in 16-byte pieces.
 // IPW values of i per wave (IB * IPW per workgroup): with IPW = 2 every B
 // fragment read from LDS feeds two matrix-core operations, which halves the
 // LDS traffic per flop where that traffic, not the matrix cores, is the limit.
