@@ -132,7 +132,7 @@ __device__ void fft_stages(T* br, T* bi, int M, int L, int CW, const T* __restri
 // A_k = sum_{q<M} x^_q e^(-i pi (2k+1) q / M) for k < M/2 and every real column
 // of X [M+1][nc], with x^_0 = (X_0 - X_M)/2. Output planar [M/2][nc].
 template <class T>
-__global__ __launch_bounds__(256) void k_fft_fwd(int nc, int M, int L, int CW, const T* __restrict__ X,
+__global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, const T* __restrict__ X,
                                                  const T* __restrict__ twist, const T* __restrict__ tw,
                                                  T* __restrict__ Are, T* __restrict__ Aim) {
     extern __shared__ unsigned char sm_raw[];
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_fft_fwd(int nc, int M, int L, int CW, c
 // out_q = (1/M) sum_{k<M} C_k e^(i pi (2k+1) q / M), q < M, for real outputs
 // whose spectra satisfy C_(M-1-k) = conj(C_k); input planar [M/2][nc].
 template <class T>
-__global__ __launch_bounds__(256) void k_fft_inv(int nc, int M, int L, int CW, const T* __restrict__ Cre,
+__global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, const T* __restrict__ Cre,
                                                  const T* __restrict__ Cim, const T* __restrict__ twist,
                                                  const T* __restrict__ tw, T* __restrict__ out) {
     extern __shared__ unsigned char sm_raw[];
@@ -662,11 +662,15 @@ int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0,
                const T* tw, hipStream_t st) {
     int L = 0;
     while ((1 << L) < M) ++L;
-    int CW = (int)(65536 / ((long)M * 2 * sizeof(T)));
+    // 128 KB of LDS per workgroup: at M = 1024 that is 16 real columns in float64
+    // (32 in float32), so every row of tau is read and written in whole
+    // 128-byte lines; 1024 threads keep the compute unit busy with one workgroup
+    int CW = (int)(131072 / ((long)M * 2 * sizeof(T)));
     if (CW < 1) CW = 1;
     if (CW > 32) CW = 32;
     const size_t smem = (size_t)CW * M * 2 * sizeof(T);
     const long blocks = ((long)nc + 2 * CW - 1) / (2 * CW);
+    const int threads = CW * M >= 4096 ? 1024 : 256;
     static bool attr[2][2] = {{false, false}, {false, false}};
     const int ti = sizeof(T) == 8 ? 0 : 1;
     if (!attr[ti][inverse]) {
@@ -675,11 +679,11 @@ int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0,
         attr[ti][inverse] = true;
     }
     if (!inverse)
-        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(256), smem, st, nc, M, L, CW, in0, twist, tw,
-                           out0, out1);
+        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, in0, twist,
+                           tw, out0, out1);
     else
-        hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(256), smem, st, nc, M, L, CW, in0, in1, twist,
-                           tw, out0);
+        hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, in0, in1,
+                           twist, tw, out0);
     LAUNCH_CHECK();
     return NEGF_OK;
 }
