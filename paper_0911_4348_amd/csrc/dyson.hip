@@ -565,20 +565,35 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, T* G) {
 }
 
 // ------------------------------------------------------------ energy
-// part[q] = Tr[Sc(beta - tau_q) G(tau_q)], float64 products, compensated sum
+// part[q] = Tr[Sc(beta - tau_q) G(tau_q)] = sum_ij S_ij G_ji, float64 products,
+// compensated sum. G is read through LDS one 32 x 32 block at a time, so that
+// both S (block (I, J)) and G (block (J, I)) are read along their rows.
 template <class T>
 __global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T* __restrict__ Sc,
                                                        const T* __restrict__ G, double* part) {
     __shared__ double red[2 * (256 / 64) + 2];
+    __shared__ double gt[32][33];
     const int q = blockIdx.x;
     const long nn = (long)n * n;
     const T* S = Sc + (long)(n_tau - 1 - q) * nn;
     const T* g = G + (long)q * nn;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8 threads
     CSum s{0.0, 0.0};
-    for (long e = threadIdx.x; e < nn; e += 256) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        s.add((double)S[e] * (double)g[(long)j * n + i]);
-    }
+    for (int I = 0; I < n; I += 32)
+        for (int J = 0; J < n; J += 32) {
+            __syncthreads();
+            // gt[c][r] = G[J + r][I + c]: row r of block (J, I), stored transposed
+            for (int r = ty; r < 32; r += 8) {
+                const int gr = J + r, gc = I + tx;
+                gt[tx][r] = (gr < n && gc < n) ? (double)g[(long)gr * n + gc] : 0.0;
+            }
+            __syncthreads();
+            // S[I + r][J + c] * G[J + c][I + r], G from gt[r][c]
+            for (int r = ty; r < 32; r += 8) {
+                const int i = I + r, j = J + tx;
+                if (i < n && j < n) s.add((double)S[(long)i * n + j] * gt[r][tx]);
+            }
+        }
     const double tot = block_csum<256>(s, red);
     if (threadIdx.x == 0) part[q] = tot;
 }
