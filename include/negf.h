@@ -173,8 +173,9 @@ int negf_g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau, double b
  * largest entry lies in [1/2, 1)) and the result unscaled, so no slice
  * underflows before the output. NEGF_BF16 keeps a bf16 copy of the scaled
  * slices in context scratch (n_tau * n_b * 8*ceil(n_b/8) * 2 bytes), written
- * once per call. Sigma_c must not alias G. Errors: NEGF_EINVAL (n_b < 1,
- * n_tau < 2, sigma not 1 or 2, bad dtype, NULL pointers). */
+ * once per call, and takes at most 65535 slices. Sigma_c must not alias G.
+ * Errors: NEGF_EINVAL (n_b < 1, n_tau < 2, sigma not 1 or 2, bad dtype, NULL
+ * pointers, NEGF_BF16 with n_tau > 65535). */
 int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
                  const void* G, void* Sigma_c, int dtype, void* stream);
 
