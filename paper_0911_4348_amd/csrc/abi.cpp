@@ -386,6 +386,7 @@ extern "C" int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const 
     NEGF_REQUIRE(V && G && Sc, "NULL buffer");
     NEGF_REQUIRE(G != Sc, "Sigma_c must not alias G");
     NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    NEGF_REQUIRE(dtype != NEGF_BF16 || n_tau <= 65535, "n_tau = %d exceeds 65535 slices for NEGF_BF16", n_tau);
     NEGF_TRY(bind_device(ctx));
     hipStream_t st = (hipStream_t)stream;
     if (dtype == NEGF_F64)
@@ -404,6 +405,7 @@ extern "C" int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, c
     NEGF_REQUIRE(V && G && Sc, "NULL buffer");
     NEGF_REQUIRE(G != Sc, "Sigma_c must not alias G");
     NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    NEGF_REQUIRE(dtype != NEGF_BF16 || n_tau <= 65535, "n_tau = %d exceeds 65535 slices for NEGF_BF16", n_tau);
     NEGF_TRY(bind_device(ctx));
     hipStream_t st = (hipStream_t)stream;
     if (dtype == NEGF_F64)
@@ -421,6 +423,7 @@ int check_s2b_batch(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const i
     NEGF_REQUIRE(n_b && sigma && V && G && Sc, "NULL argument array");
     NEGF_REQUIRE(n_tau >= 2 && n_tau <= (1 << 20), "n_tau = %d out of range", n_tau);
     NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32 || dtype == NEGF_BF16, "bad dtype %d", dtype);
+    NEGF_REQUIRE(dtype != NEGF_BF16 || n_tau <= 65535, "n_tau = %d exceeds 65535 slices for NEGF_BF16", n_tau);
     for (int b = 0; b < batch; ++b) {
         NEGF_REQUIRE(n_b[b] >= 1 && n_b[b] <= 4096, "n_b[%d] = %d out of range [1, 4096]", b, n_b[b]);
         NEGF_REQUIRE(sigma[b] == 1 || sigma[b] == 2, "sigma[%d] must be 1 or 2", b);

@@ -140,3 +140,17 @@ def test_matrix_rate_rejects_bad_arguments(L):
     assert rc == negf.EINVAL and b"dtype" in L.negf_last_error()
     rc = L.negf_matrix_rate(C.c_void_p(1), 0, None, C.byref(ghz), None)
     assert rc == negf.EINVAL
+
+
+def test_bf16_slice_limit_checked_on_host(L):
+    """NEGF_BF16 takes at most 65535 slices; the limit is checked before any device work."""
+    fake = C.c_void_p(1)
+    rc = L.negf_sigma2b(fake, 10, 70000, 2, C.c_void_p(8), C.c_void_p(16), C.c_void_p(24), negf.BF16, None)
+    assert rc == negf.EINVAL and b"65535" in L.negf_last_error()
+    n = (C.c_int * 1)(10)
+    sg = (C.c_int * 1)(2)
+    ptrs = (C.c_void_p * 1)(8)
+    outs = (C.c_void_p * 1)(24)
+    Gs = (C.c_void_p * 1)(16)
+    rc = L.negf_sigma2b_batched(fake, 1, n, 70000, sg, ptrs, Gs, outs, negf.BF16, None)
+    assert rc == negf.EINVAL and b"65535" in L.negf_last_error()
