@@ -240,6 +240,30 @@ def test_dyson_step_uniform(ctx, torch_mod, route):
     assert abs(N - D.particle_number(G, 2)) < 1e-12
 
 
+def test_dyson_step_bench_size(ctx, torch_mod):
+    """The Dyson step at the benchmark's size and launch configuration (n_b = 199,
+    1025 points, Fourier route, alpha = 0.3, symmetrised), whole tensor against
+    the oracle. The step is linear in Sigma_c, so a seeded symmetric Sigma_c of
+    the size Sigma-2B produces stands in for an oracle Sigma-2B evaluation."""
+    s = W.config_sigma_bench()
+    print(f"dyson step at n_b={s.n_b}, {s.M + 1} points", flush=True)
+    setup, o = SC.run_hf(s)
+    x, Wt, T, v, V = negf.fedvr_build_system(s)
+    hfs = negf.hf(ctx, dev(torch_mod, T), dev(torch_mod, v), dev(torch_mod, V), s.n_elec, s.sigma, s.beta)
+    tg = negf.TauGrid.of_system(s)
+    G = W.synthetic_G(s.n_b, s.M, s.beta, seed=2)
+    Sc = 0.01 * W.random_symmetric_slices(s.n_b, s.M + 1, 31)
+    h = T + np.diag(v)
+    Gout, E, N = negf.dyson_step(ctx, tg, s.sigma, dev(torch_mod, h), dev(torch_mod, V), hfs, dev(torch_mod, G),
+                                 dev(torch_mod, Sc), 0.3, conv=negf.CONV_FFT)
+    got = host(Gout)
+    ref = D.dyson_step(D.DysonContext(setup, o, "uniform"), G, Sc, 0.3, route="fft")
+    assert relerr(got, ref) < TOL64
+    Eref = D.gm_energy(setup.h, setup.V, s.sigma, G, Sc, setup.tau)
+    assert abs(E - Eref) < TOL64 * abs(Eref)
+    assert abs(N - D.particle_number(G, s.sigma)) < 1e-11
+
+
 def test_dyson_step_power_mesh(ctx, torch_mod):
     s = W.he_1d(half_width=6.0, n_e=3, n_g=5, beta=10.0).with_(tau_kind="power", u=6, p=3)
     r, G, Sc = _dyson_inputs(s)
