@@ -262,6 +262,15 @@ def test_dyson_step_bench_size(ctx, torch_mod):
     Eref = D.gm_energy(setup.h, setup.V, s.sigma, G, Sc, setup.tau)
     assert abs(E - Eref) < TOL64 * abs(Eref)
     assert abs(N - D.particle_number(G, s.sigma)) < 1e-11
+    # the float32 step of the mixed form, same input and reference
+    f32 = torch_mod.float32
+    G32, E32, _ = negf.dyson_step(ctx, tg, s.sigma, dev(torch_mod, h), dev(torch_mod, V), hfs,
+                                  dev(torch_mod, G, f32), dev(torch_mod, Sc, f32), 0.3, conv=negf.CONV_FFT,
+                                  dtype="f32")
+    err = relerr(host(G32), ref)
+    print(f"dyson f32 at bench size: normwise error {err:.2e}")
+    assert err < 1e-5
+    assert abs(E32 - Eref) < 1e-5 * abs(Eref)
 
 
 def test_dyson_step_power_mesh(ctx, torch_mod):
