@@ -28,6 +28,25 @@ def ed_ground_energy(T, v, V):
     return float(np.linalg.eigvalsh(two_electron_hamiltonian(T, v, V))[0])
 
 
+def ed_ground_energy_iterative(T, v, V, start=None, tol=1e-11):
+    """The same lowest eigenvalue for grids too large for a dense n_b^2 x n_b^2
+    matrix: Lanczos (scipy's eigsh) on the operator X -> T X + X T + W o X,
+    W_ab = v_a + v_b + V_ab, acting on the two-electron amplitude X_ab.
+    ``start`` (optional) is a starting amplitude, e.g. the product of the
+    lowest one-electron orbital with itself."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    n = T.shape[0]
+    Wd = v[:, None] + v[None, :] + V
+
+    def mv(x):
+        X = x.reshape(n, n)
+        return (T @ X + X @ T + Wd * X).reshape(-1)
+
+    op = LinearOperator((n * n, n * n), matvec=mv, dtype=np.float64)
+    v0 = None if start is None else np.asarray(start, dtype=np.float64).reshape(-1)
+    return float(eigsh(op, k=1, which="SA", tol=tol, v0=v0, return_eigenvectors=False)[0])
+
+
 def mo_eri(C, V):
     """(pq|rs) = sum_ab C_ap C_aq V_ab C_br C_bs for the DVR tensor (aa|bb) = V_ab."""
     P = np.einsum("ap,aq->apq", C, C)

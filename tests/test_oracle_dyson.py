@@ -134,3 +134,66 @@ def test_power_mesh_converges_to_uniform_limit():
     errs = [abs(SC.scf(base.with_(tau_kind="power", u=u, p=3), fixed_iters=2).E - ref)
             for u in (4, 8)]
     assert errs[1] < errs[0] / 2.5
+
+
+def _interp_args(t, u):
+    """Off-node arguments on a power mesh: random ones, the midpoints of every
+    interval, and arguments a hair inside either side of every block boundary
+    (node index a multiple of u)."""
+    rng = np.random.default_rng(17)
+    s = list(rng.uniform(t[0], t[-1], size=200))
+    s += list(0.5 * (t[1:] + t[:-1]))
+    for b in range(u, len(t) - 1, u):
+        for side in (-1, 1):
+            h = t[b + side] - t[b] if side > 0 else t[b] - t[b - 1]
+            s.append(t[b] + side * 1e-6 * h)
+    return np.array(s)
+
+
+def test_lagrange4_on_power_mesh_is_cubic_exact_with_the_stencil_in_its_block():
+    """Reading of the power-mesh convolution (Sigma_c between grid points): 4-point
+    Lagrange interpolation inside the uniform block of the argument. Pinned with
+    the textbook remainder: for f(x) = (x - s)^4 the interpolant at s equals
+    -prod_m (s - t_m) exactly (f'''' = 24), and any cubic is reproduced. The
+    stencil is 4 consecutive nodes of the block that holds s and brackets s."""
+    u, p, beta = 6, 4, 10.0
+    t = fedvr.tau_power(beta, u, p)
+    c = np.array([0.7, -1.3, 0.4, 0.05])
+    for s in _interp_args(t, u):
+        nodes, w = D.lagrange4(t, s, u)
+        tn = t[nodes]
+        # stencil: consecutive, inside one uniform block, around s
+        assert np.all(np.diff(nodes) == 1)
+        blk = nodes[0] // u
+        assert nodes[-1] <= (blk + 1) * u
+        assert t[blk * u] <= s <= t[min((blk + 1) * u, len(t) - 1)]
+        assert tn[0] <= s <= tn[3]
+        a = int(np.searchsorted(t, s, side="right")) - 1
+        if a - 1 >= blk * u and a + 2 <= (blk + 1) * u:
+            assert tn[1] <= s <= tn[2]
+        # equal spacing inside the stencil (the block is uniform)
+        h = np.diff(tn)
+        assert np.max(np.abs(h - h[0])) < 1e-12 * h[0]
+        # cubic exactness
+        f = lambda x: c[0] + x * (c[1] + x * (c[2] + x * c[3]))
+        assert abs(w @ f(tn) - f(s)) < 1e-12 * (1.0 + abs(f(s)))
+        # the remainder of the quartic (x - s)^4
+        q = (tn - s) ** 4
+        omega = np.prod(s - tn)
+        assert abs(w @ q + omega) < 1e-9 * max(np.max(np.abs(w * q)), 1e-300)
+
+
+def test_lagrange4_fourth_order_off_node():
+    """Interpolating a smooth function off the nodes converges like h^4 (error
+    ratio 16 when the block step halves)."""
+    beta, p = 6.0, 2
+    errs = []
+    for u in (8, 16, 32):
+        t = fedvr.tau_power(beta, u, p)
+        s_all = 0.5 * (t[1:] + t[:-1]) + 0.17 * np.diff(t)
+        e = 0.0
+        for s in s_all:
+            nodes, w = D.lagrange4(t, s, u)
+            e = max(e, abs(w @ np.exp(-0.8 * t[nodes]) - np.exp(-0.8 * s)))
+        errs.append(e)
+    assert 13.0 < errs[0] / errs[1] < 19.0 and 13.0 < errs[1] / errs[2] < 19.0
