@@ -148,6 +148,13 @@ def soft_coulomb_potential(x, centres, charges, soft=1.0) -> np.ndarray:
     return v
 
 
+def harmonic_potential(x, omega) -> np.ndarray:
+    """Harmonic confinement (1/2) omega^2 x^2 (the trap of the paper's conclusion),
+    diagonal in the DVR like any local potential (Eq. vmat)."""
+    x = np.asarray(x, dtype=np.float64)
+    return 0.5 * omega * omega * x * x
+
+
 # ----------------------------------------------------------------------------- O6
 def interaction_direct(x, ee_soft=1.0, scale=1.0) -> np.ndarray:
     """Diagonal-pair interaction kernel V_ab = u(|x_a - x_b|), u = scale / sqrt(d^2 + ee_soft)
@@ -241,6 +248,8 @@ class Setup:
         self.W = self.grid.W
         self.T = kinetic(self.grid)
         self.v = soft_coulomb_potential(self.x, sysd.centres, sysd.charges, sysd.soft)
+        if getattr(sysd, "omega", 0.0):
+            self.v = self.v + harmonic_potential(self.x, sysd.omega)
         self.V = interaction_direct(self.x, sysd.ee_soft, sysd.ee_scale)
         self.h = self.T + np.diag(self.v)
         if sysd.tau_kind == "uniform":

@@ -30,6 +30,7 @@ class System:
     ``tau_kind`` is "uniform" (M intervals, M + 1 points) or "power"
     (2 u p + 1 points clustered at both ends of [0, beta]).
     ``e_nn`` is a constant added once to the total energy (nuclear repulsion).
+    ``omega`` > 0 adds a harmonic confinement (1/2) omega^2 x^2 to v.
     """
 
     name: str
@@ -48,6 +49,7 @@ class System:
     u: int = 0
     p: int = 0
     e_nn: float = 0.0
+    omega: float = 0.0
 
     @property
     def n_e(self) -> int:
@@ -117,6 +119,16 @@ def h3p_1d(R=1.8, half_width=60.0, n_e=60, n_g=6, beta=100.0, tau_kind="power",
     return System(name="h3p1d", bounds=b, n_g=n_g, centres=np.array([-R, 0.0, R]),
                   charges=np.array([1.0, 1.0, 1.0]), beta=beta, tau_kind=tau_kind,
                   M=M, u=u, p=p, e_nn=5.0 / (2.0 * R))
+
+
+def harmonic_trap(n_elec=20.0, omega=1.0, half_width=12.0, n_e=101, n_g=5, beta=20.0, M=256,
+                  ee_scale=0.5) -> System:
+    """n_elec fermions (closed shells, both spins) in the trap (1/2) omega^2 x^2 with
+    the soft-Coulomb interaction of Sec. 3 scaled by ee_scale; no nuclei. The
+    default grid has n_b = 504 (101 equal elements x 6 GLL points on [-12, 12]),
+    the size class the paper's conclusion names (N <= 20, n_b > 500)."""
+    return System(name="trap1d", bounds=uniform_bounds(half_width, n_e), n_g=n_g, centres=np.zeros(0),
+                  charges=np.zeros(0), ee_scale=ee_scale, n_elec=n_elec, beta=beta, M=M, omega=omega)
 
 
 def config_he() -> System:
