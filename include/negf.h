@@ -98,6 +98,7 @@ typedef struct {
     double soft;             /* v(x) = -sum Z_c / sqrt((x - X_c)^2 + soft) */
     double ee_soft;          /* V(x,x') = ee_scale / sqrt((x - x')^2 + ee_soft) */
     double ee_scale;
+    double omega;            /* harmonic confinement: v(x) += omega^2 x^2 / 2 (0: none) */
 } negf_potential_t;
 
 /* FE-DVR setup (Sec. 2.1-2.2): GLL nodes and weights per element (Eqs. xim,
@@ -159,6 +160,26 @@ int negf_g0_build(negf_ctx* ctx, int n_b, int n_tau, const double* tau, double b
                   const double* eps, const double* C, double mu, void* G0, int dtype,
                   void* stream);
 
+/* ------------------------------------------------------------------ density */
+/* One-electron density at the DVR nodes (Sec. 2.3: from the equal-time Green's
+ * function; Fig. 3b): n(x_a) = -sigma G_aa(beta^-) / W_a, the only basis
+ * function non-zero at x_a being chi_a(x_a) = 1/sqrt(W_a).
+ * W (dev, float64, n_b) summed GLL weights from fedvr_build; G (dev, dtype
+ * NEGF_F64 or NEGF_F32, [n_tau][n_b][n_b]), only its last slice is read;
+ * n (dev, float64, n_b) output. Stream-ordered, no synchronisation.
+ * Errors: NEGF_EINVAL. */
+int negf_density(negf_ctx* ctx, int n_b, int n_tau, int sigma, const double* W, const void* G, int dtype,
+                 double* n, void* stream);
+
+/* The density n(x) = sigma sum_ab chi_a(x) chi_b(x) rho_ab at arbitrary points
+ * of the box, from the per-spin density matrix rho = -G(beta^-) (host, float64,
+ * n_b*n_b) through the Lobatto shape functions of the element holding x
+ * (Sec. 2.1, Eq. basis). x (host, n_x) points; n_out (host, n_x); points
+ * outside [bounds[0], bounds[n_e]] give 0 (Dirichlet ends). Host computation.
+ * Errors: NEGF_EINVAL. */
+int negf_density_at(const negf_grid_t* grid, const double* rho, int sigma, int n_x, const double* x,
+                    double* n_out);
+
 /* ------------------------------------------------------------------ Sigma 2B */
 /* Second-Born correlation self-energy for every tau slice (Sec. 2.3,
  * Eq. sigma2ndb with the interaction lines at equal times):
@@ -183,7 +204,7 @@ int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
  * per workgroup x column-chunk width) on the given input and stores the fastest
  * for (dtype, n_b) in the context; later negf_sigma2b calls with that dtype and
  * n_b use it. Arguments as for negf_sigma2b (Sigma_c is overwritten). *best
- * (host, nullable) receives the chosen index, ms (host, nullable, 11 entries) the
+ * (host, nullable) receives the chosen index, ms (host, nullable, 13 entries) the
  * measured times (-1 for a configuration that does not fit or does not exist
  * for this dtype). Synchronises. */
 int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
@@ -195,7 +216,12 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
  * k-panels; 6, 7 (NEGF_F32 and NEGF_BF16 only) = 4 waves with two values of i
  * each x 112- or 64-column chunks; 8, 9, 10 (NEGF_F64 only) = float64 vector-ALU
  * tiles: 8 waves x 40 x 40 blocks of M^(i), 4 waves with two values of i each x
- * 40 x 40 or 32 x 32 blocks. */
+ * 40 x 40 or 32 x 32 blocks; 11, 12 (NEGF_F64 only) = 8 or 4 values of i x
+ * 208-column chunks whose k-panels are staged by direct global-to-LDS loads,
+ * double-buffered, from zero-padded copies of G and V kept in context scratch
+ * (n_tau * np^2 + np^2 doubles, np = n_b rounded up to 16; n_b <= 240 for 11).
+ * The float64 matrix-core tiles (0-5, 11, 12) run on the four-block 4x4x4
+ * float64 MFMA shape. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
 /* Sustained rate of the matrix-core operation the Sigma-2B kernels issue for
@@ -231,7 +257,8 @@ int negf_sigma2b_batched_set_config(negf_ctx* ctx, int batch, const int* n_b, in
 /* Autotuner for negf_sigma2b_batched: times each tile configuration on the
  * first pair_lim slice pairs of every system (0: all pairs), keeps the fastest
  * for this dtype and multiset of n_b. Sigma_c is overwritten (partly). *best,
- * ms[11] (host, nullable) as for negf_sigma2b_tune. Synchronises. */
+ * ms[13] (host, nullable) as for negf_sigma2b_tune (configurations 11 and 12 do
+ * not exist in the persistent kernel: -1). Synchronises. */
 int negf_sigma2b_batched_tune(negf_ctx* ctx, int batch, const int* n_b, int n_tau, const int* sigma,
                               const void* const* V, const void* const* G, void* const* Sigma_c,
                               int dtype, int pair_lim, int* best, double* ms, void* stream);
@@ -314,7 +341,20 @@ typedef struct {
     int tune;                /* 1: run the batch tile autotuner first (once per batch shape) */
     int no_graph;            /* 1: launch every iteration directly (no HIP graphs) */
     int progress;            /* 1: one line per iteration on stderr (systems left, max |dE|, ms) */
+    int stop_rule;           /* NEGF_STOP_DELTA (0): |E_k - E_(k-1)| < tol;
+                                NEGF_STOP_CONTRACTION (1): |d_k| rho / (1 - rho) < tol,
+                                d_k = E_k - E_(k-1), rho = max(|d_k / d_(k-1)|,
+                                |d_(k-1) / d_(k-2)|) < 1, k >= 3 (or d_k = 0): a bound
+                                on |E_k - E_inf| for a geometric tail */
+    int guard;               /* 1: runaway guard (Sec. 3.1, stable N): if E_k or N_k is not
+                                finite, |N_k - n_elec| > n_elec / 2, or |dE| grew three
+                                times in a row, restart from G0 with alpha halved, at
+                                most 3 times per system (steps before a restart count
+                                in iters) */
 } negf_opts_t;
+
+#define NEGF_STOP_DELTA       0
+#define NEGF_STOP_CONTRACTION 1
 
 typedef struct {
     int iter;                /* Dyson steps done before this energy */
@@ -325,8 +365,9 @@ typedef struct {
 
 /* Whole self-consistent second-Born ground state (Sec. 2.3): fedvr_build,
  * negf_hf, G = G0 (or G_guess), then for k = 0, 1, ...:
- *   Sigma_c = Sigma_2B[G_k]; E_k = E_GM[G_k]; stop if k >= 1 and
- *   |E_k - E_(k-1)| < tol; else G_(k+1) = Dyson step of G_k.
+ *   Sigma_c = Sigma_2B[G_k]; E_k = E_GM[G_k]; stop if k >= 1 and the
+ *   stopping rule holds (opts.stop_rule: |E_k - E_(k-1)| < tol, or the
+ *   contraction-aware bound); else G_(k+1) = Dyson step of G_k.
  * Mixed form (dtype F32/BF16): the loop runs in float32 until tol, then
  * float64 steps continue from that G until refine_tol.
  * G_guess (dev, float64, [n_tau][n_b][n_b], nullable) replaces G0 as the start.

@@ -20,7 +20,7 @@ the library:
       half the mixing parameter, at most three times; the steps before a
       restart are counted in ``iters`` and listed in ``wasted``. Signs of a
       runaway: E_k or N_k not finite, the particle number off by more than a
-      quarter (|N_k - N| > N/4; Sec. 3.1 asks for a stable N), or the energy
+      half (|N_k - N| > N/2; Sec. 3.1 asks for a stable N), or the energy
       change growing three times in a row (|d_k| > |d_(k-1)| > |d_(k-2)| > |d_(k-3)|).
       A converged fixed point whose N differs from N by less than that is
       accepted: the chemical potential stays at its HF value.
@@ -47,7 +47,7 @@ def run_hf(sysd, setup=None):
     return setup, hf
 
 
-N_GUARD = 0.25          # relative particle-number drift that triggers a restart
+N_GUARD = 0.5           # relative particle-number drift that triggers a restart
 MAX_BACKOFF = 3         # restarts with halved mixing
 
 

@@ -24,6 +24,10 @@ OK, EINVAL, ENODEV, EHIP, ENAN, ENOCONV, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 TAU_UNIFORM, TAU_POWER = 0, 1
 CONV_AUTO, CONV_FFT, CONV_DIRECT = 0, 1, 2
+STOP_DELTA, STOP_CONTRACTION = 0, 1
+_STOP = {"delta": STOP_DELTA, "contraction": STOP_CONTRACTION, STOP_DELTA: STOP_DELTA,
+         STOP_CONTRACTION: STOP_CONTRACTION}
+N_CFG = 13              # Sigma-2B tile configurations (negf_sigma2b_set_config)
 
 _NAMES = {OK: "NEGF_OK", EINVAL: "NEGF_EINVAL", ENODEV: "NEGF_ENODEV", EHIP: "NEGF_EHIP",
           ENAN: "NEGF_ENAN", ENOCONV: "NEGF_ENOCONV", ENOMEM: "NEGF_ENOMEM"}
@@ -42,7 +46,7 @@ class GridT(C.Structure):
 
 class PotentialT(C.Structure):
     _fields_ = [("n_c", C.c_int), ("X", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)),
-                ("soft", C.c_double), ("ee_soft", C.c_double), ("ee_scale", C.c_double)]
+                ("soft", C.c_double), ("ee_soft", C.c_double), ("ee_scale", C.c_double), ("omega", C.c_double)]
 
 
 class TauGridT(C.Structure):
@@ -61,7 +65,8 @@ class OptsT(C.Structure):
                 ("fixed_iters", C.c_int), ("dtype", C.c_int), ("conv_algo", C.c_int),
                 ("symmetrize", C.c_int), ("refine_tol", C.c_double), ("hf_tol", C.c_double),
                 ("hf_max_iter", C.c_int), ("guess_params", C.c_void_p), ("guess_scale", C.c_double),
-                ("tune", C.c_int), ("no_graph", C.c_int), ("progress", C.c_int)]
+                ("tune", C.c_int), ("no_graph", C.c_int), ("progress", C.c_int), ("stop_rule", C.c_int),
+                ("guard", C.c_int)]
 
 
 class IterLogT(C.Structure):
@@ -81,6 +86,8 @@ _SIGS = {
     "negf_ctx_scratch_bytes": (C.c_int, [_VP, C.POINTER(C.c_size_t)]),
     "negf_fedvr_size": (C.c_int, [C.c_int, C.c_int, _IP]),
     "fedvr_build": (C.c_int, [C.POINTER(GridT), C.POINTER(PotentialT), _DP, _DP, _DP, _DP, _DP]),
+    "negf_density": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, C.c_int, _VP, _VP]),
+    "negf_density_at": (C.c_int, [C.POINTER(GridT), _DP, C.c_int, C.c_int, _DP, _DP]),
     "negf_tau_count": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _IP]),
     "negf_tau_grid": (C.c_int, [C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, _DP]),
     "negf_hf": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_double, C.c_int, C.c_double, C.c_double,
@@ -213,19 +220,19 @@ def fedvr_size(n_e: int, n_g: int) -> int:
     return n.value
 
 
-def _grid_pot(bounds, n_g, centres, charges, soft, ee_soft, ee_scale):
+def _grid_pot(bounds, n_g, centres, charges, soft, ee_soft, ee_scale, omega=0.0):
     b = np.ascontiguousarray(bounds, dtype=np.float64)
     X = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1)
     Z = np.ascontiguousarray(charges, dtype=np.float64).reshape(-1)
     g = GridT(len(b) - 1, n_g, _dptr(b))
     p = PotentialT(len(X), _dptr(X) if len(X) else None, _dptr(Z) if len(Z) else None,
-                   soft, ee_soft, ee_scale)
+                   soft, ee_soft, ee_scale, omega)
     return g, p, (b, X, Z)
 
 
-def fedvr_build(bounds, n_g, centres, charges, soft=1.0, ee_soft=1.0, ee_scale=1.0):
+def fedvr_build(bounds, n_g, centres, charges, soft=1.0, ee_soft=1.0, ee_scale=1.0, omega=0.0):
     """Host FE-DVR setup; returns numpy (x, W, T, v, V)."""
-    g, p, keep = _grid_pot(bounds, n_g, centres, charges, soft, ee_soft, ee_scale)
+    g, p, keep = _grid_pot(bounds, n_g, centres, charges, soft, ee_soft, ee_scale, omega)
     n = fedvr_size(g.n_e, n_g)
     x, W, v = np.zeros(n), np.zeros(n), np.zeros(n)
     T, V = np.zeros((n, n)), np.zeros((n, n))
@@ -235,7 +242,18 @@ def fedvr_build(bounds, n_g, centres, charges, soft=1.0, ee_soft=1.0, ee_scale=1
 
 def fedvr_build_system(sysd):
     return fedvr_build(sysd.bounds, sysd.n_g, sysd.centres, sysd.charges, sysd.soft, sysd.ee_soft,
-                       sysd.ee_scale)
+                       sysd.ee_scale, getattr(sysd, "omega", 0.0))
+
+
+def density_at(bounds, n_g, rho, sigma, xs) -> np.ndarray:
+    """negf_density_at: n(x) at the points xs from the per-spin density matrix rho (host)."""
+    b = np.ascontiguousarray(bounds, dtype=np.float64)
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    x = np.ascontiguousarray(xs, dtype=np.float64)
+    out = np.zeros(len(x))
+    g = GridT(len(b) - 1, n_g, _dptr(b))
+    _check(lib().negf_density_at(C.byref(g), _dptr(r), int(sigma), len(x), _dptr(x), _dptr(out)))
+    return out
 
 
 def tau_grid(kind, beta, M=0, u=0, p=0) -> np.ndarray:
@@ -347,7 +365,7 @@ def sigma2b_tune(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=N
     if out is None:
         out = torch.empty_like(G)
     best = C.c_int()
-    ms = (C.c_double * 11)()
+    ms = (C.c_double * N_CFG)()
     _check(lib().negf_sigma2b_tune(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
                                    _DT[dtype], C.byref(best), ms, _stream(stream)))
     return best.value, list(ms)
@@ -373,6 +391,17 @@ def dyson_step(ctx: Context, tg: TauGrid, sigma, h, V, hfs: HFState, G_in, Sc, a
     return G_out, (E.value if want_energy else None), (N.value if want_energy else None)
 
 
+def density(ctx: Context, W, G, sigma, dtype="f64", out=None, stream=None):
+    """negf_density: n at the DVR nodes from G(beta^-); W, G device tensors."""
+    torch = _torch()
+    n_tau, n, _ = G.shape
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=G.device)
+    _check(lib().negf_density(ctx.handle, n, n_tau, int(sigma), _dev_ptr(W), _dev_ptr(G), _DT[dtype], _dev_ptr(out),
+                              _stream(stream)))
+    return out
+
+
 def energy(ctx: Context, tg: TauGrid, sigma, h, V, G, Sc, dtype="f64", stream=None):
     n = G.shape[1]
     E, N = C.c_double(), C.c_double()
@@ -396,7 +425,7 @@ class SCFOut:
 def system_struct(sysd):
     """Build the C negf_system_t for a workloads.System (returns struct, keep-alive)."""
     g, p, keep = _grid_pot(sysd.bounds, sysd.n_g, sysd.centres, sysd.charges, sysd.soft, sysd.ee_soft,
-                           sysd.ee_scale)
+                           sysd.ee_scale, getattr(sysd, "omega", 0.0))
     kind = TAU_UNIFORM if sysd.tau_kind == "uniform" else TAU_POWER
     s = SystemT(g, p, float(sysd.n_elec), int(sysd.sigma), float(sysd.beta), kind, int(sysd.M),
                 int(sysd.u), int(sysd.p), float(sysd.e_nn))
@@ -404,10 +433,10 @@ def system_struct(sysd):
 
 
 def _opts(alpha, tol, max_iter, fixed_iters, dtype, conv, symmetrize, refine_tol, guess=None, guess_scale=1.0,
-          tune=False, graphs=True, progress=False):
+          tune=False, graphs=True, progress=False, stop="delta", guard=False):
     return OptsT(float(alpha), float(tol), int(max_iter), int(fixed_iters), _DT[dtype], int(conv),
                  int(symmetrize), float(refine_tol), 0.0, 0, _dev_ptr(guess), float(guess_scale), int(tune),
-                 0 if graphs else 1, int(progress))
+                 0 if graphs else 1, int(progress), _STOP[stop], int(bool(guard)))
 
 
 def _records(logs, base, count):
@@ -418,20 +447,21 @@ def _records(logs, base, count):
 def scf(ctx: Context, sysd, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
         conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
         allow_noconv=False, guess=None, guess_scale=1.0, graphs=True, tune=True, progress=False,
-        stream=None) -> SCFOut:
-    """negf_scf for a workloads.System (guess: learned-guess parameters on the device)."""
+        stop="delta", guard=False, stream=None) -> SCFOut:
+    """negf_scf for a workloads.System (guess: learned-guess parameters on the device;
+    stop: "delta" or "contraction"; guard: the particle-number guard)."""
     out = scf_batched(ctx, [sysd], alpha=alpha, tol=tol, max_iter=max_iter, fixed_iters=fixed_iters, dtype=dtype,
                       conv=conv, symmetrize=symmetrize, refine_tol=refine_tol,
                       G_guess=None if G_guess is None else [G_guess], want_G=want_G, allow_noconv=allow_noconv,
                       guess=guess, guess_scale=guess_scale, graphs=graphs, tune=tune, single=True,
-                      progress=progress, stream=stream)
+                      progress=progress, stop=stop, guard=guard, stream=stream)
     return out[0]
 
 
 def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed_iters=0, dtype="f64",
                 conv=CONV_AUTO, symmetrize=True, refine_tol=0.0, G_guess=None, want_G=True,
                 allow_noconv=False, guess=None, guess_scale=1.0, tune=True, graphs=True, single=False,
-                progress=False, stream=None):
+                progress=False, stop="delta", guard=False, stream=None):
     """negf_scf_batched (single=True: negf_scf) for a list of workloads.System; returns a list of SCFOut."""
     torch = _torch()
     B = len(systems)
@@ -441,7 +471,7 @@ def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed
         structs[b] = st_
         keep.append(k)
     o = _opts(alpha, tol, max_iter, fixed_iters, dtype, conv, symmetrize, refine_tol, guess, guess_scale, tune,
-              graphs, progress)
+              graphs, progress, stop, guard)
     Gs = [torch.empty((sd.n_tau, sd.n_b, sd.n_b), dtype=torch.float64, device="cuda") if want_G else None
           for sd in systems]
     Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
@@ -451,7 +481,7 @@ def scf_batched(ctx: Context, systems, alpha=0.3, tol=1e-8, max_iter=1000, fixed
     E, N, hE, hmu = np.zeros(B), np.zeros(B), np.zeros(B), np.zeros(B)
     it, ln = np.zeros(B, dtype=np.int32), np.zeros(B, dtype=np.int32)
     stat = np.zeros(B, dtype=np.int32)
-    cap = (fixed_iters if fixed_iters else max_iter) + max_iter + 4
+    cap = ((fixed_iters if fixed_iters else max_iter) + max_iter + 4) * (4 if guard else 1)
     logs = (IterLogT * (B * cap))()
     if single:
         rc = lib().negf_scf(ctx.handle, C.byref(structs[0]), C.byref(o), guess_p[0] if guess_p else None,
@@ -512,7 +542,7 @@ def sigma2b_batched_tune(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, pa
     Gp = (C.c_void_p * B)(*[_dev_ptr(g) for g in Gs])
     Sp = (C.c_void_p * B)(*[_dev_ptr(o) for o in outs])
     best = C.c_int()
-    ms = np.zeros(11)
+    ms = np.zeros(N_CFG)
     _check(lib().negf_sigma2b_batched_tune(ctx.handle, B, n.ctypes.data_as(_IP), int(Gs[0].shape[0]),
                                            sg.ctypes.data_as(_IP), Vp, Gp, Sp, _DT[dtype], int(pair_lim),
                                            C.byref(best), _dptr(ms), _stream(stream)))

@@ -222,6 +222,7 @@ extern "C" int fedvr_build(const negf_grid_t* g, const negf_potential_t* pot, do
     NEGF_REQUIRE(pot->n_c >= 0 && pot->n_c <= 64, "n_c out of range");
     NEGF_REQUIRE(pot->n_c == 0 || (pot->X && pot->Z), "centres/charges NULL");
     NEGF_REQUIRE(pot->soft > 0 && pot->ee_soft > 0, "softening must be positive");
+    NEGF_REQUIRE(pot->omega >= 0 && std::isfinite(pot->omega), "omega must be finite and >= 0");
     const int N = g->n_g, n_e = g->n_e;
     std::vector<double> xr, wr, D;
     gll(N, xr, wr, D);
@@ -273,6 +274,7 @@ extern "C" int fedvr_build(const negf_grid_t* g, const negf_potential_t* pot, do
                 double d = x[k] - pot->X[c];
                 s -= pot->Z[c] / std::sqrt(d * d + pot->soft);
             }
+            s += 0.5 * pot->omega * pot->omega * x[k] * x[k];          // harmonic confinement
             v_out[k] = s;                                              // Eq. vmat
         }
     }
@@ -282,6 +284,63 @@ extern "C" int fedvr_build(const negf_grid_t* g, const negf_potential_t* pot, do
                 double d = x[a] - x[b];
                 V_out[(size_t)a * n_b + b] = pot->ee_scale / std::sqrt(d * d + pot->ee_soft);
             }
+    }
+    return NEGF_OK;
+}
+
+// ============================================================== density (host)
+extern "C" int negf_density_at(const negf_grid_t* g, const double* rho, int sigma, int n_x, const double* xs,
+                               double* n_out) {
+    NEGF_REQUIRE(g && rho && (n_x == 0 || (xs && n_out)), "NULL argument");
+    NEGF_REQUIRE(sigma == 1 || sigma == 2, "sigma must be 1 or 2");
+    NEGF_REQUIRE(n_x >= 0, "n_x < 0");
+    int n_b = 0;
+    NEGF_TRY(negf_fedvr_size(g->n_e, g->n_g, &n_b));
+    NEGF_REQUIRE(g->bounds != nullptr, "bounds is NULL");
+    for (int e = 0; e < g->n_e; ++e)
+        NEGF_REQUIRE(g->bounds[e + 1] > g->bounds[e] && std::isfinite(g->bounds[e + 1]),
+                     "element bounds must increase (element %d)", e);
+    const int N = g->n_g, n_e = g->n_e;
+    std::vector<double> xr, wr, D;
+    gll(N, xr, wr, D);
+    auto gidx = [&](int e, int m) -> int {
+        if (m == 0) return e == 0 ? -1 : e * N - 1;
+        if (m == N) return e == n_e - 1 ? -1 : e * N + N - 1;
+        return e * N + m - 1;
+    };
+    std::vector<double> W(n_b, 0.0);
+    for (int e = 0; e < n_e; ++e)
+        for (int m = 0; m <= N; ++m) {
+            const int k = gidx(e, m);
+            if (k >= 0) W[k] += 0.5 * wr[m] * (g->bounds[e + 1] - g->bounds[e]);
+        }
+    std::vector<double> xe(N + 1), chi(N + 1);
+    std::vector<int> id(N + 1);
+    for (int p = 0; p < n_x; ++p) {
+        const double x = xs[p];
+        if (!(x >= g->bounds[0] && x <= g->bounds[n_e])) {     // outside the box (Dirichlet)
+            n_out[p] = 0.0;
+            continue;
+        }
+        int e = (int)(std::upper_bound(g->bounds, g->bounds + n_e + 1, x) - g->bounds) - 1;
+        e = std::min(std::max(e, 0), n_e - 1);
+        const double a = g->bounds[e], b = g->bounds[e + 1], h = b - a;
+        for (int m = 0; m <= N; ++m) xe[m] = 0.5 * (h * xr[m] + (b + a));
+        for (int m = 0; m <= N; ++m) {
+            // Lobatto shape function f_m(x) (Sec. 2.1) over the basis normalisation
+            double f = 1.0;
+            for (int j = 0; j <= N; ++j)
+                if (j != m) f *= (x - xe[j]) / (xe[m] - xe[j]);
+            id[m] = gidx(e, m);
+            chi[m] = id[m] >= 0 ? f / std::sqrt(W[id[m]]) : 0.0;
+        }
+        double s = 0.0;
+        for (int m = 0; m <= N; ++m) {
+            if (id[m] < 0) continue;
+            for (int k = 0; k <= N; ++k)
+                if (id[k] >= 0) s += chi[m] * chi[k] * rho[(size_t)id[m] * n_b + id[k]];
+        }
+        n_out[p] = sigma * s;
     }
     return NEGF_OK;
 }
@@ -394,6 +453,19 @@ extern "C" int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const 
                                    (double*)Sc, false, st);
     return sigma2b_run<float>(ctx, n_b, n_tau, sigma, (const float*)V, (const float*)G,
                               (float*)Sc, dtype == NEGF_BF16, st);
+}
+
+extern "C" int negf_density(negf_ctx* ctx, int n_b, int n_tau, int sigma, const double* W, const void* G, int dtype,
+                            double* n, void* stream) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(n_b >= 1 && n_b <= 65536, "n_b = %d out of range", n_b);
+    NEGF_REQUIRE(n_tau >= 2, "n_tau = %d < 2", n_tau);
+    NEGF_REQUIRE(sigma == 1 || sigma == 2, "sigma must be 1 or 2");
+    NEGF_REQUIRE(W && G && n, "NULL buffer");
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32, "dtype must be NEGF_F64 or NEGF_F32");
+    NEGF_TRY(bind_device(ctx));
+    if (dtype == NEGF_F64) return density_run<double>(n_b, n_tau, sigma, W, (const double*)G, n, (hipStream_t)stream);
+    return density_run<float>(n_b, n_tau, sigma, W, (const float*)G, n, (hipStream_t)stream);
 }
 
 extern "C" int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V, const void* G,

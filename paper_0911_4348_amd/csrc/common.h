@@ -123,6 +123,9 @@ template <class T>
 int energy_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, const double* h,
                const double* V, const T* G, const T* Sc, double* E, double* N, hipStream_t st);
 
+template <class T>
+int density_run(int n_b, int n_tau, int sigma, const double* W, const T* G, double* out, hipStream_t st);
+
 // ---------------------------------------------------------------- small kernels
 template <class Tout, class Tin>
 int convert(const Tin* in, Tout* out, size_t n, hipStream_t st);

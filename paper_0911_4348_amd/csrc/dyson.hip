@@ -627,6 +627,14 @@ __global__ __launch_bounds__(256) void k_energy_final(int n, int n_tau, int sigm
     }
 }
 
+// ------------------------------------------------------------ density at the nodes
+template <class T>
+__global__ __launch_bounds__(256) void k_density(int n, int sigma, const double* __restrict__ W,
+                                                 const T* __restrict__ GM, double* __restrict__ out) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a < n) out[a] = -sigma * (double)GM[(long)a * n + a] / W[a];
+}
+
 // ------------------------------------------------------------ host helpers
 void grid_tables(const negf_tau_grid_t* tg, std::vector<double>& w, std::vector<double>& hL,
                  std::vector<double>& hR) {
@@ -849,6 +857,16 @@ int energy_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const
     *N = hres[1];
     return NEGF_OK;
 }
+
+template <class T>
+int density_run(int n, int n_tau, int sigma, const double* W, const T* G, double* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_density<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sigma, W,
+                       G + (long)(n_tau - 1) * n * n, out);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
+template int density_run<double>(int, int, int, const double*, const double*, double*, hipStream_t);
+template int density_run<float>(int, int, int, const double*, const float*, double*, hipStream_t);
 
 template int dyson_run<double>(negf_ctx*, const negf_tau_grid_t*, int, int, const double*, const double*,
                                const double*, const double*, double, const double*, const double*, const double*,

@@ -75,7 +75,33 @@ struct Sys {
     bool restarted = false;  // learned start abandoned for G0 after a non-finite energy
     int wasted = 0;          // steps spent before such a restart
     int log_n = 0;
+    double alpha = 0.3;      // mixing of this system (halved by each guard restart)
+    int backoffs = 0;        // guard restarts so far
+    double dh[4] = {0, 0, 0, 0};   // last energy changes of the current run, newest first
+    int nd = 0;
 };
+
+constexpr double kNGuard = 0.5;    // relative particle-number drift that restarts a run
+constexpr int kMaxBackoff = 3;
+
+// The guard's runaway test: E or N not finite, N off by more than kNGuard, or
+// the energy change growing three times in a row.
+bool runaway(double E, double N, double n_elec, const double* dh, int nd) {
+    if (!std::isfinite(E) || !std::isfinite(N)) return true;
+    if (std::fabs(N - n_elec) > kNGuard * n_elec) return true;
+    return nd >= 4 && std::fabs(dh[0]) > std::fabs(dh[1]) && std::fabs(dh[1]) > std::fabs(dh[2]) &&
+           std::fabs(dh[2]) > std::fabs(dh[3]);
+}
+
+// The stopping test on the last energy changes (dh[0] newest, nd of them).
+bool stop_test(int rule, const double* dh, int nd, double tol) {
+    if (nd < 1) return false;
+    if (rule == NEGF_STOP_DELTA) return std::fabs(dh[0]) < tol;
+    if (dh[0] == 0.0) return true;
+    if (nd < 3 || dh[1] == 0.0 || dh[2] == 0.0) return false;
+    const double rho = std::max(std::fabs(dh[0] / dh[1]), std::fabs(dh[1] / dh[2]));
+    return rho < 1.0 && std::fabs(dh[0]) * rho / (1.0 - rho) < tol;
+}
 
 struct GraphSlot {
     std::string key;
@@ -148,6 +174,8 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
     NEGF_REQUIRE(o->conv_algo >= NEGF_CONV_AUTO && o->conv_algo <= NEGF_CONV_DIRECT, "bad conv_algo");
     NEGF_REQUIRE(log_cap >= 0, "log_cap < 0");
     NEGF_REQUIRE(!o->guess_params || !G_guess, "give either G_guess or guess_params, not both");
+    NEGF_REQUIRE(o->stop_rule == NEGF_STOP_DELTA || o->stop_rule == NEGF_STOP_CONTRACTION, "bad stop_rule %d",
+                 o->stop_rule);
     const negf_system_t& s0 = systems[0];
     int n_tau = 0;
     std::vector<int> nb(batch);
@@ -322,6 +350,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
     for (Sys& y : S) {
         y.phase = !y.hf_ok ? PH_DONE : (low ? PH_LOW : PH_F64);
         y.limit = fixed ? o->fixed_iters : o->max_iter;
+        y.alpha = o->alpha;
         n_hf_fail += !y.hf_ok;
     }
     if (n_hf_fail) set_error("HF not converged for %d system(s); those were not iterated", n_hf_fail);
@@ -429,7 +458,31 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             y.E = E;
             y.N = N;
             const int step = y.wasted + (y.phase == PH_F64 ? y.steps_low : 0) + y.k;
-            if ((!std::isfinite(E) || !std::isfinite(N)) && y.learned && !y.restarted) {
+            const double dE = std::isnan(y.E_prev) ? NAN : E - y.E_prev;
+            if (y.k >= 1) {
+                for (int h = 3; h > 0; --h) y.dh[h] = y.dh[h - 1];
+                y.dh[0] = dE;
+                y.nd = std::min(y.nd + 1, 4);
+            }
+            if (o->guard && y.backoffs < kMaxBackoff && runaway(E, N, systems[y.b].n_elec, y.dh, y.nd)) {
+                // particle-number guard: restart from G0 with half the mixing
+                if (log && log_n && y.log_n < log_cap)
+                    log[(size_t)y.b * log_cap + y.log_n++] =
+                        negf_iter_log_t{step, y.phase == PH_LOW ? o->dtype : NEGF_F64, E, NAN, N, ms};
+                y.wasted = step + 1;
+                y.backoffs++;
+                y.alpha *= 0.5;
+                NEGF_TRY(g0_build<double>(ctx, y.n, n_tau, tau.data(), systems[y.b].beta, y.eps, y.C, y.mu, y.G, st));
+                if (low) NEGF_TRY(to_f32(y.G, y.Gf, y.nn * n_tau, st));
+                y.phase = low ? PH_LOW : PH_F64;
+                y.k = 0;
+                y.steps_low = 0;
+                y.E_prev = NAN;
+                y.nd = 0;
+                y.limit = fixed ? o->fixed_iters : o->max_iter;
+                continue;
+            }
+            if (!o->guard && (!std::isfinite(E) || !std::isfinite(N)) && y.learned && !y.restarted) {
                 // the learned start left the basin of the iteration: restart from G0
                 y.wasted = step + 1;
                 y.restarted = true;
@@ -450,13 +503,12 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
                 y.phase = PH_DONE;
                 continue;
             }
-            const double dE = std::isnan(y.E_prev) ? NAN : E - y.E_prev;
             if (std::isfinite(dE)) max_dE = std::max(max_dE, std::fabs(dE));
             // a fixed-count run ignores the tolerance; the float64 refinement of
             // the mixed form has its own
             const double tol = (low && y.phase == PH_F64 && o->refine_tol > 0) ? o->refine_tol : o->tol;
             bool stop = false;
-            if (!fixed && y.k >= 1 && std::fabs(dE) < tol) {
+            if (!fixed && y.k >= 1 && stop_test(o->stop_rule, y.dh, y.nd, tol)) {
                 y.conv = true;
                 stop = true;
             }
@@ -479,6 +531,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
                     y.phase = PH_F64;
                     y.k = 0;
                     y.E_prev = NAN;
+                    y.nd = 0;
                     y.conv = false;
                     y.limit = o->max_iter > y.steps_low ? o->max_iter - y.steps_low : 1;
                 }
@@ -493,19 +546,20 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
         }
         // (b) Dyson step of every system that goes on
         if (!dy_lo.empty() || !dy_hi.empty()) {
+            // the mixing of each system is part of the recorded segment
             std::string keyD = "D";
-            for (int r : dy_lo) keyD += " l" + std::to_string(r);
-            for (int r : dy_hi) keyD += " h" + std::to_string(r);
+            for (int r : dy_lo) keyD += " l" + std::to_string(r) + "a" + std::to_string(S[r].backoffs);
+            for (int r : dy_hi) keyD += " h" + std::to_string(r) + "a" + std::to_string(S[r].backoffs);
             NEGF_TRY(run_segment(gD, keyD, graphs, gS, st, [&]() -> int {
                 for (int r : dy_lo) {
                     const Sys& y = S[r];
                     NEGF_TRY(dyson_run<float>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.eps, y.C, y.mu, y.Sig0,
-                                              y.Gf, y.Scf, o->alpha, o->symmetrize, o->conv_algo, y.Gf, st));
+                                              y.Gf, y.Scf, y.alpha, o->symmetrize, o->conv_algo, y.Gf, st));
                 }
                 for (int r : dy_hi) {
                     const Sys& y = S[r];
                     NEGF_TRY(dyson_run<double>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.eps, y.C, y.mu,
-                                               y.Sig0, y.G, y.Sc, o->alpha, o->symmetrize, o->conv_algo, y.G, st));
+                                               y.Sig0, y.G, y.Sc, y.alpha, o->symmetrize, o->conv_algo, y.G, st));
                 }
                 return NEGF_OK;
             }));

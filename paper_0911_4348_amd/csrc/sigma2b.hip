@@ -319,12 +319,29 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                     const T* Gs = reinterpret_cast<const T*>(stage0 + buf * SB);
                     // k-steps of 4 that hold real rows (uniform across the workgroup)
                     const int nks = min(BK / 4, (n - pn * BK + 3) >> 2);
+                    // float64 runs on the four-block 4x4x4 shape, which sustains
+                    // about 1.5x the rate of the 16x16x4 one on gfx950: four of
+                    // them (rows 4r .. 4r+3 of the l-tile) make one 16 x 16 tile.
+                    // With the same A rows in all four blocks, block b holds
+                    // columns 4b .. 4b+3, so B and the result use the lanes and
+                    // registers of the 16x16x4 shape (row 4r + lane/16, column
+                    // lane % 16); A row 4r + lane % 4, k = lane / 16.
+                    constexpr bool QUAD = MODE == MODE_F64;
+                    constexpr int NA = QUAD ? 4 : 1;
+                    // row groups of 4 that hold real rows (uniform): the padded
+                    // groups of the last l-tile are skipped
+                    const int nrg = QUAD ? min(4, (n - l0 + 3) >> 2) : 1;
                     // operand fragments in two register sets: the LDS reads of
                     // k-step ks + 1 are in flight while the matrix cores work on ks
-                    T fa[2], fv[2][IPW], fb[2][NJB];
+                    T fa[2][NA], fv[2][IPW], fb[2][NJB];
                     auto frag = [&](int ks, int s) {
                         const int kk = ks * 4 + lg;
-                        fa[s] = Ab[lc * (BK + 1) + kk];
+                        if constexpr (QUAD) {
+#pragma unroll
+                            for (int r = 0; r < NA; ++r) fa[s][r] = Ab[(4 * r + (lane & 3)) * (BK + 1) + kk];
+                        } else {
+                            fa[s][0] = Ab[lc * (BK + 1) + kk];
+                        }
 #pragma unroll
                         for (int p = 0; p < IPW; ++p) fv[s][p] = Vk[(w * IPW + p) * BK + kk];
 #pragma unroll
@@ -336,13 +353,30 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
                         if (ks < nks) {
                             const int s = ks & 1;
                             if (ks + 1 < nks) frag(ks + 1, s ^ 1);
-                            T a[IPW];
+                            if constexpr (QUAD) {
 #pragma unroll
-                            for (int p = 0; p < IPW; ++p) a[p] = fa[s] * fv[s][p];
+                                for (int r = 0; r < NA; ++r) {
+                                    if (r < nrg) {
 #pragma unroll
-                            for (int jb = 0; jb < NJB; ++jb)
+                                        for (int p = 0; p < IPW; ++p) {
+                                            const double a = fa[s][r] * fv[s][p];
 #pragma unroll
-                                for (int p = 0; p < IPW; ++p) acc[p][jb] = Mma<T>::mma(a[p], fb[s][jb], acc[p][jb]);
+                                            for (int jb = 0; jb < NJB; ++jb)
+                                                acc[p][jb][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                                                    a, fb[s][jb], acc[p][jb][r], 0, 0, 0);
+                                        }
+                                    }
+                                }
+                            } else {
+                                T a[IPW];
+#pragma unroll
+                                for (int p = 0; p < IPW; ++p) a[p] = fa[s][0] * fv[s][p];
+#pragma unroll
+                                for (int jb = 0; jb < NJB; ++jb)
+#pragma unroll
+                                    for (int p = 0; p < IPW; ++p)
+                                        acc[p][jb] = Mma<T>::mma(a[p], fb[s][jb], acc[p][jb]);
+                            }
                         }
                     }
                 }
@@ -496,6 +530,309 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
             }
         }
     }
+}
+
+// ---------------------------------------------------------------- float64, direct-to-LDS staging
+// The float64 tile with the same arithmetic as s2b_tile (four-block 4x4x4
+// MFMAs, same epilogue and direct term), but every operand panel reaches LDS
+// by direct global->LDS loads (global_load_lds_dwordx4: each lane moves 16
+// bytes, the wave's 64 pieces land contiguously at the address in M0), so no
+// register holds staged data. The k-panels are double-buffered: the loads of
+// panel p+1 are in flight while the matrix cores work on panel p, with one
+// barrier per panel. The loads read zero-padded copies of G and V (rows and
+// columns padded to np = n rounded up to 16), so every piece is in bounds and
+// the padding is exact zeros.
+namespace dma {
+
+constexpr int BK = 16;                       // k-panel
+// A panel [16 l][16 k]: 16-byte piece kp (k = 2 kp, 2 kp + 1) of row l is
+// stored at piece kp ^ (l & 7) of that row, so the fragment reads of four
+// rows 128 bytes apart spread over the banks.
+__device__ __forceinline__ int a_index(int l, int k) { return l * 16 + ((((k >> 1) ^ (l & 7))) << 1) + (k & 1); }
+
+template <int IB, int JB>
+struct Layout {
+    static constexpr int JW = JB * 16;
+    static constexpr int B_EL = BK * JW;             // B panel [BK][jw] (row stride jw of the chunk)
+    static constexpr int A_EL = 16 * 16;
+    static constexpr int V_EL = IB * 16;             // V panel [IB][BK]
+    static constexpr int STAGE_EL = B_EL + A_EL + V_EL;
+    static constexpr int VT_EL = 16 * JW;            // V tile of the epilogue [16][jw]
+    // one column chunk: the direct term is accumulated in the l-tile loop,
+    // in a further [IB][np] array
+    static size_t bytes(int np) {
+        const int npj = (np + JW - 1) / JW * JW;
+        const size_t d = np <= JW ? (size_t)IB * np : 0;
+        return sizeof(double) * (2 * (size_t)STAGE_EL + VT_EL + 3 * (size_t)IB * np + (size_t)IB * npj + d);
+    }
+};
+
+__device__ __forceinline__ void load16(const double* g, double* lds_wave) {
+    __builtin_amdgcn_global_load_lds(static_cast<const void*>(g), (__attribute__((address_space(3))) void*)lds_wave,
+                                     16, 0, 0);
+}
+
+// Pieces 0 .. count-1 of a contiguous LDS region, piece c from src(c); the
+// waves take 64 consecutive pieces each in turn.
+template <int NT, class F>
+__device__ __forceinline__ void copy(double* dst, int count, int tid, F src) {
+    const int w = tid >> 6, lane = tid & 63;
+    for (int base = w * 64; base < count; base += NT) {
+        const int c = base + lane;
+        if (c < count) load16(src(c), dst + 2 * base);
+    }
+}
+
+__device__ __forceinline__ void wait_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <int IB, int JB>
+__device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int iblk, double sigma,
+                                     const double* __restrict__ Vp, const double* __restrict__ Gp,
+                                     const double* __restrict__ G, double* __restrict__ Sc, double* smem) {
+    typedef Layout<IB, JB> L;
+    constexpr int NT = IB * 64;
+    constexpr int JW = L::JW;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lc = lane & 15, lg = lane >> 4;
+    const int q = pair, qb = n_tau - 1 - pair;
+    const bool middle = q == qb;
+    const long nn = (long)n * n, pp = (long)np * np;
+    const double* Gq = Gp + (long)q * pp;            // padded slices
+    const double* Gb = Gp + (long)qb * pp;
+    const int npj = (np + JW - 1) / JW * JW;
+    double* stage = smem;                            // [2][STAGE_EL]
+    double* Vt = stage + 2 * L::STAGE_EL;            // [16][jw]
+    double* T1s = Vt + L::VT_EL;                     // [IB][np]
+    double* Xs = T1s + IB * np;                      // [IB][np]
+    double* XPs = Xs + IB * np;                      // [IB][np]
+    double* Gbi = XPs + IB * np;                     // [IB][npj]
+    double* Ds = Gbi + IB * npj;                     // [IB][np], one column chunk only
+    const bool one_chunk = np <= JW;
+    const int i = iblk * IB + w;                     // this wave's row (< np)
+
+    for (int e = tid; e < 3 * IB * np; e += NT) T1s[e] = 0.0;
+    if (one_chunk)
+        for (int e = tid; e < IB * np; e += NT) Ds[e] = 0.0;
+    for (int e = tid; e < IB * npj; e += NT) {
+        const int rr = e / npj, j = e - rr * npj;
+        Gbi[e] = j < np ? Gb[(long)(iblk * IB + rr) * np + j] : 0.0;
+    }
+    const int npan = (n + BK - 1) / BK;
+
+    for (int j0 = 0; j0 < np; j0 += JW) {
+        const int jw = min(JW, np - j0);
+        const int njb = jw >> 4;
+        // Element offsets of this lane's 16-byte pieces, the same for every panel
+        // of the chunk: piece base + lane of a [16][jw] block (B panel, V tile)
+        // is row c / (jw/2), columns 2 (c % (jw/2)) + 0, 1; A and V pieces as in
+        // the panel layouts. A piece that does not exist gets -1.
+        constexpr int NPB = (16 * (JW / 2) + NT - 1) / NT;      // B / V-tile pieces per lane
+        int offb[NPB];
+        {
+            const int hp = jw >> 1;
+#pragma unroll
+            for (int t = 0; t < NPB; ++t) {
+                const int c = w * 64 + t * NT + lane;
+                const int kk = c / hp, jp = c - kk * hp;
+                offb[t] = c < 16 * hp ? kk * np + j0 + 2 * jp : -1;
+            }
+        }
+        const int ca = tid - (NT - 128);             // A pieces: the last two waves
+        const int offa = ca >= 0 ? (ca >> 3) * np + 2 * ((ca & 7) ^ ((ca >> 3) & 7)) : -1;
+        const int cv = tid - (NT - 192);             // V pieces: the wave before them
+        const int offv = (cv >= 0 && cv < IB * 8) ? (iblk * IB + (cv >> 3)) * np + 2 * (cv & 7) : -1;
+        // all 16 x jw pieces of a [16][jw] block of M (row stride np) into dst
+        auto copy_rows = [&](double* dst, const double* M) {
+#pragma unroll
+            for (int t = 0; t < NPB; ++t)
+                if (offb[t] >= 0) load16(M + offb[t], dst + 2 * (w * 64 + t * NT));
+        };
+        auto issue = [&](int l0, int pn, int buf) {
+            double* sb = stage + buf * L::STAGE_EL;
+            const int k0 = pn * BK;
+            copy_rows(sb, Gq + (long)k0 * np);
+            if (offa >= 0) load16(Gb + (long)l0 * np + k0 + offa, sb + L::B_EL + 2 * (ca & ~63));
+            if (offv >= 0) load16(Vp + k0 + offv, sb + L::B_EL + L::A_EL + 2 * (cv & ~63));
+        };
+        int g = 0;                                   // panels started in this chunk
+        issue(0, 0, 0);
+        wait_loads();
+        __syncthreads();
+        for (int l0 = 0; l0 < n; l0 += 16) {
+            // V rows l0 .. l0+15 of this chunk for the epilogue; G_il for this wave's rows
+            copy_rows(Vt, Vp + (long)l0 * np);
+            double gil[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gil[r] = Gq[(long)i * np + l0 + Mma<double>::row(lane, r)];
+            dv4 acc[JB];
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) acc[jb] = Mma<double>::zero();
+#pragma unroll 1
+            for (int pn = 0; pn < npan; ++pn, ++g) {
+                const int cur = g & 1;
+                if (pn + 1 < npan) issue(l0, pn + 1, cur ^ 1);
+                else if (l0 + 16 < n) issue(l0 + 16, 0, cur ^ 1);
+                const double* Bs = stage + cur * L::STAGE_EL;
+                const double* As = Bs + L::B_EL;
+                const double* Vs = As + L::A_EL;
+                // A branch-free body: the padding rows and columns of the copies
+                // are zeros, so the ragged last panel and l-tile are computed
+                // whole, and in a narrow last chunk the column blocks past jw read
+                // other staged values (finite; their results are never used).
+                // The operand reads of k-step ks + 1 are issued before the products
+                // of ks.
+                double fa[2][4], fv[2], fb[2][JB];
+                auto frag = [&](int ks, int s) {
+                    const int kk = ks * 4 + lg;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) fa[s][r] = As[a_index(4 * r + (lane & 3), kk)];
+                    fv[s] = Vs[w * 16 + kk];
+#pragma unroll
+                    for (int jb = 0; jb < JB; ++jb) fb[s][jb] = Bs[kk * jw + jb * 16 + lc];
+                };
+                frag(0, 0);
+#pragma unroll
+                for (int ks = 0; ks < BK / 4; ++ks) {
+                    const int s = ks & 1;
+                    if (ks + 1 < BK / 4) frag(ks + 1, s ^ 1);
+                    double a[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[r] = fa[s][r] * fv[s];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int jb = 0; jb < JB; ++jb)
+                            acc[jb][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[r], fb[s][jb], acc[jb][r], 0, 0, 0);
+                }
+                wait_loads();
+                __syncthreads();
+            }
+            // diagonal of M^(i) for rows l0 .. l0+15 if this chunk holds those columns
+            if (l0 >= j0 && l0 < j0 + jw) {
+                const int jd = (l0 - j0) >> 4;
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb)
+                    if (jb == jd) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (Mma<double>::row(lane, r) == lc) T1s[w * np + l0 + lc] = acc[jb][r];
+                    }
+            }
+            double xp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                if (jb < njb) {
+                    const double gbi = Gbi[w * npj + j0 + jb * 16 + lc];
+                    double xc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double vm = Vt[Mma<double>::row(lane, r) * jw + jb * 16 + lc] * acc[jb][r];
+                        xp[r] += gbi * vm;
+                        xc += gil[r] * vm;
+                    }
+                    const double sx = sum4x16(xc);
+                    if (lg == 0) Xs[w * np + j0 + jb * 16 + lc] += sx;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double sx = sum16(xp[r]);
+                if (lc == 0) XPs[w * np + l0 + Mma<double>::row(lane, r)] += sx;
+            }
+            if (one_chunk) {
+                // direct term D_ij += sum_l T1_il V_lj over this tile's 16 rows l,
+                // with the V rows already in Vt (this wave wrote T1 above; its own
+                // LDS operations complete in order)
+                constexpr int DM = (JW + 63) / 64;
+#pragma unroll
+                for (int m = 0; m < DM; ++m) {
+                    const int j = lane + 64 * m;
+                    if (j < jw) {
+                        double d = Ds[w * np + j];
+#pragma unroll
+                        for (int ll = 0; ll < 16; ++ll) d += T1s[w * np + l0 + ll] * Vt[ll * jw + j];
+                        Ds[w * np + j] = d;
+                    }
+                }
+            }
+            __syncthreads();                         // Vt is read; the next l-tile may replace it
+        }
+    }
+
+    // direct term D_ij = sum_l T1_il V_lj (V tiles double-buffered through the
+    // stage area), then one store per output element
+    constexpr int DM = (JW + 63) / 64;
+    for (int j0 = 0; j0 < np; j0 += JW) {
+        const int jw = min(JW, np - j0);
+        double d[DM];
+#pragma unroll
+        for (int m = 0; m < DM; ++m) d[m] = 0.0;
+        if (one_chunk) {
+#pragma unroll
+            for (int m = 0; m < DM; ++m)
+                if (lane + 64 * m < jw) d[m] = Ds[w * np + lane + 64 * m];
+        } else {
+            auto issue_v = [&](int l0, int buf) {
+                copy<NT>(stage + buf * L::STAGE_EL, 8 * jw, tid, [&](int c) {
+                    const int hp = jw >> 1, ll = c / hp, jp = c - ll * hp;
+                    return Vp + (long)(l0 + ll) * np + j0 + 2 * jp;
+                });
+            };
+            issue_v(0, 0);
+            int b = 0;
+            for (int l0 = 0; l0 < n; l0 += 16, b ^= 1) {
+                wait_loads();
+                __syncthreads();
+                if (l0 + 16 < n) issue_v(l0 + 16, b ^ 1);
+                const double* Vv = stage + b * L::STAGE_EL;
+                for (int ll = 0; ll < 16; ++ll) {
+                    const double t = T1s[w * np + l0 + ll];      // zero beyond n
+#pragma unroll
+                    for (int m = 0; m < DM; ++m)
+                        if (lane + 64 * m < jw) d[m] += t * Vv[ll * jw + lane + 64 * m];
+                }
+            }
+        }
+        if (i < n) {
+            const double* Gu = G + (long)q * nn;
+            const double* Gbu = G + (long)qb * nn;
+            double* Sq = Sc + (long)q * nn;
+            double* Sqb = Sc + (long)qb * nn;
+#pragma unroll
+            for (int m = 0; m < DM; ++m) {
+                const int j = j0 + lane + 64 * m;
+                if (lane + 64 * m < jw && j < n) {
+                    const long ij = (long)i * n + j;
+                    Sq[ij] = sigma * Gu[ij] * d[m] - Xs[w * np + j];
+                    if (!middle) Sqb[ij] = sigma * Gbu[ij] * d[m] - XPs[w * np + j];
+                }
+            }
+        }
+        __syncthreads();                             // before the next chunk reuses the stage area
+    }
+}
+
+}  // namespace dma
+
+// Zero-padded copy of a stack of n x n matrices into np x np blocks.
+__global__ __launch_bounds__(256) void k_pad_copy(int n, int np, long count, const double* __restrict__ src,
+                                                  double* __restrict__ dst) {
+    const long pp = (long)np * np;
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < count * pp; e += (long)gridDim.x * 256) {
+        const long s = e / pp, rc = e - s * pp;
+        const int r = (int)(rc / np), c = (int)(rc - (long)r * np);
+        dst[e] = (r < n && c < n) ? src[s * n * n + (long)r * n + c] : 0.0;
+    }
+}
+
+template <int IB, int JB>
+__global__ __launch_bounds__(IB * 64, 2) void k_sigma2b_dma(int n, int np, int n_tau, int n_iblk, double sigma,
+                                                            const double* __restrict__ Vp,
+                                                            const double* __restrict__ Gp,
+                                                            const double* __restrict__ G, double* __restrict__ Sc) {
+    extern __shared__ __align__(16) double smem_d[];
+    const long lb = xcd_remap(blockIdx.x, gridDim.x);
+    dma::tile<IB, JB>(n, np, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, Vp, Gp, G, Sc, smem_d);
 }
 
 // ---------------------------------------------------------------- float64 on the vector ALUs
@@ -884,8 +1221,53 @@ int slices_to_bf16(int n, int n_tau, const float* G, const int* ex, __bf16* gh, 
 // 4: 8 x 112, 5: 8 x 208 (double-buffered staging);
 // 6: 4 waves x 2 values of i x 112 cols, 7: 4 x 2 x 64 cols (float32 and bf16 only);
 // 8: 8 waves x 40 x 40 vector-ALU tiles, 9: 4 waves x 2 values of i x 40 x 40,
-// 10: 4 x 2 x 32 x 32 (float64 only).
-constexpr int kNumCfg = 11;
+// 10: 4 x 2 x 32 x 32 (float64 only); 11, 12: 8 or 4 waves x 208 columns with
+// direct-to-LDS double-buffered staging from padded copies (float64 only, not
+// in the persistent kernel).
+constexpr int kNumCfg = 13;
+
+// float64 tile with direct-to-LDS staging: zero-padded copies of G and V in
+// context scratch (one pass each per call), then one workgroup per (slice pair,
+// block of IB rows i).
+template <int IB, int JB>
+int launch_dma_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, const double* G, double* Sc,
+                   hipStream_t st) {
+    const int np = (n + 15) & ~15;
+    const size_t smem = dma::Layout<IB, JB>::bytes(np);
+    if (smem > 160 * 1024) {
+        set_error("n_b = %d too large for this Sigma-2B tile configuration's LDS budget", n);
+        return NEGF_EINVAL;
+    }
+    const int n_pairs = (n_tau + 1) / 2;
+    const int n_iblk = (n + IB - 1) / IB;
+    const long blocks = (long)n_pairs * n_iblk;
+    if (blocks > 0x7fffffffL) {
+        set_error("too many workgroups");
+        return NEGF_EINVAL;
+    }
+    double *Gp = nullptr, *Vp = nullptr;
+    NEGF_TRY(scratch_t(ctx, "s2b_gpad", (size_t)n_tau * np * np, &Gp));
+    NEGF_TRY(scratch_t(ctx, "s2b_vpad", (size_t)np * np, &Vp));
+    auto pad = [&](const double* src, double* dst, long count) -> int {
+        long b = (count * np * np + 255) / 256;
+        if (b > 65536) b = 65536;
+        hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)b), dim3(256), 0, st, n, np, count, src, dst);
+        LAUNCH_CHECK();
+        return NEGF_OK;
+    };
+    NEGF_TRY(pad(G, Gp, n_tau));
+    NEGF_TRY(pad(V, Vp, 1));
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b_dma<IB, JB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sigma2b_dma<IB, JB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, np, n_tau, n_iblk,
+                       (double)sigma, Vp, Gp, G, Sc);
+    LAUNCH_CHECK();
+    return NEGF_OK;
+}
 
 template <int IB, int TL, int IPW>
 int launch_valu_cfg(int n, int n_tau, int sigma, const double* V, const double* G, double* Sc, hipStream_t st) {
@@ -942,13 +1324,16 @@ int launch_cfg(int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V, cons
     return NEGF_OK;
 }
 
+// ex_fixed (nullable): caller-provided storage for the per-slice exponents of
+// the low-precision modes (at least n_tau ints); otherwise context scratch.
 template <int MODE>
 int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>::T* V,
-           const typename Cfg<MODE>::T* G, typename Cfg<MODE>::T* Sc, int cfg, hipStream_t st) {
-    int* ex = nullptr;
+           const typename Cfg<MODE>::T* G, typename Cfg<MODE>::T* Sc, int cfg, hipStream_t st,
+           int* ex_fixed = nullptr) {
+    int* ex = ex_fixed;
     LowP lp{nullptr, nullptr, 0};
     if (MODE != MODE_F64) {
-        NEGF_TRY(scratch_t(ctx, "s2b_ex", n_tau, &ex));
+        if (!ex) NEGF_TRY(scratch_t(ctx, "s2b_ex", n_tau, &ex));
         hipLaunchKernelGGL(k_slice_exponent, dim3(n_tau), dim3(256), 0, st, n, (const float*)G, ex);
         LAUNCH_CHECK();
         lp.ex = ex;
@@ -975,6 +1360,8 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
                 if (cfg == 8) return launch_valu_cfg<8, 5, 1>(n, n_tau, sigma, Vd, Gd, Sd, st);
                 if (cfg == 9) return launch_valu_cfg<4, 5, 2>(n, n_tau, sigma, Vd, Gd, Sd, st);
                 if (cfg == 10) return launch_valu_cfg<4, 4, 2>(n, n_tau, sigma, Vd, Gd, Sd, st);
+                if (cfg == 11) return launch_dma_cfg<8, 13>(ctx, n, n_tau, sigma, Vd, Gd, Sd, st);
+                if (cfg == 12) return launch_dma_cfg<4, 13>(ctx, n, n_tau, sigma, Vd, Gd, Sd, st);
                 set_error("tile configuration %d is for float32 and bf16 only", cfg);
                 return NEGF_EINVAL;
             } else {
@@ -1014,7 +1401,7 @@ namespace {
 
 template <class T>
 int sigma2b_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16, int cfg,
-                hipStream_t st);
+                hipStream_t st, int* ex_fixed = nullptr);
 
 template <class T>
 int sigma2b_run(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16,
@@ -1027,11 +1414,12 @@ int sigma2b_run(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T*
 
 template <class T>
 int sigma2b_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, bool bf16, int cfg,
-                hipStream_t st) {
+                hipStream_t st, int* ex_fixed) {
     if (sizeof(T) == 8) return launch<MODE_F64>(ctx, n, n_tau, sigma, (const double*)V, (const double*)G, (double*)Sc, cfg, st);
     if (bf16) return launch<MODE_BF16>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st);
-    return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st);
+    return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st, ex_fixed);
 }
+
 
 // Time every tile configuration on the caller's input (after one untimed
 // launch each) and remember the fastest for (mode, n_b) in the context.
@@ -1157,6 +1545,11 @@ int launch_batched(const S2BBatch& pl, int cfg, hipStream_t st) {
                 if (cfg == 8) return launch_batched_valu_cfg<8, 5, 1>(pl, st);
                 if (cfg == 9) return launch_batched_valu_cfg<4, 5, 2>(pl, st);
                 if (cfg == 10) return launch_batched_valu_cfg<4, 4, 2>(pl, st);
+                if (cfg == 11 || cfg == 12) {
+                    set_error("tile configuration %d (staged padded copies) is not available in the persistent kernel",
+                              cfg);
+                    return NEGF_EINVAL;
+                }
                 set_error("tile configuration %d is for float32 and bf16 only", cfg);
                 return NEGF_EINVAL;
             } else {

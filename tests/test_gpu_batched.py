@@ -98,7 +98,8 @@ def test_sigma2b_batched_tuner(ctx, torch_mod):
     best, ms = negf.sigma2b_batched_tune(ctx, Vd, Gd, 2, pair_lim=4)
     assert best not in (6, 7) and ms[best] > 0 and all(m == -1.0 or m > 0 for m in ms)
     assert ms[6] == -1.0 and ms[7] == -1.0           # float32/bf16-only configurations
-    assert all(m > 0 for m in ms[8:])                # float64 vector-ALU tiles
+    assert all(m > 0 for m in ms[8:11])              # float64 vector-ALU tiles
+    assert ms[11] == -1.0 and ms[12] == -1.0         # staged-copy tiles: single-system kernel only
     outs = negf.sigma2b_batched(ctx, Vd, Gd, 2)
     for V, G, o in zip(Vs, Gs, outs):
         assert relerr(host(o), S.sigma2b(V, G, 2)) < TOL64

@@ -90,3 +90,41 @@ def test_learned_start_with_wrong_electron_count_falls_back_to_hf_start(ctx, tor
     assert lg_run.status == negf.OK
     assert lg_run.iters == hf_run.iters
     assert lg_run.E == hf_run.E
+
+
+def test_contraction_stop_matches_oracle(ctx):
+    """The contraction-aware stopping rule stops at the same step as the oracle's."""
+    s = W.config_he()
+    ref = SC.scf(s, tol=1e-7, stop="contraction")
+    out = negf.scf(ctx, s, tol=1e-7, stop="contraction")
+    print(f"contraction rule: {out.iters} steps (oracle {ref.iters}), E = {out.E:.12f}")
+    assert out.status == negf.OK and out.iters == ref.iters
+    assert abs(out.E - ref.E) < 1e-10 * abs(ref.E)
+
+
+def test_guard_restart_matches_oracle(ctx, torch_mod):
+    """Runaway guard: a start with a quarter of the electrons is replaced by G0 with
+    alpha halved, in the library as in the oracle (same steps, same result)."""
+    s = W.config_he()
+    setup, hf, G0 = SC.hf_start(s)
+    ref = SC.scf(s, alpha=0.3, tol=1e-8, G_init=0.25 * G0, guard=True, setup=setup, hf=hf)
+    g = torch_mod.from_numpy(np.ascontiguousarray(0.25 * G0)).cuda()
+    out = negf.scf(ctx, s, alpha=0.3, tol=1e-8, G_guess=g, guard=True)
+    print(f"guard: {out.iters} steps (oracle {ref.iters}, {ref.backoffs} restart)")
+    assert ref.backoffs == 1 and out.status == negf.OK and out.iters == ref.iters
+    assert abs(out.E - ref.E) < 1e-10 * abs(ref.E)
+    assert np.max(np.abs(out.G.cpu().numpy() - ref.G)) < 1e-9 * np.max(np.abs(ref.G))
+
+
+def test_density_at_nodes_matches_oracle(ctx, torch_mod):
+    """negf_density on an SCF iterate: n(x_a) = -sigma G_aa(beta^-) / W_a."""
+    from oracle import observables as O
+    s = W.config_he()
+    ref = SC.scf(s, fixed_iters=3)
+    out = negf.scf(ctx, s, fixed_iters=3)
+    x, Wt, T, v, V = negf.fedvr_build_system(s)
+    n = negf.density(ctx, torch_mod.from_numpy(Wt).cuda(), out.G, 2).cpu().numpy()
+    nref = O.density_nodes(ref.G, ref.setup.W, 2)
+    assert np.max(np.abs(n - nref)) < 1e-10 * np.max(nref)
+    n32 = negf.density(ctx, torch_mod.from_numpy(Wt).cuda(), out.G.float(), 2, dtype="f32").cpu().numpy()
+    assert np.max(np.abs(n32 - nref)) < 1e-6 * np.max(nref)

@@ -61,10 +61,10 @@ def test_sigma2b_f64(ctx, torch_mod, n, n_tau):
     assert relerr(host(out), ref) < TOL64
 
 
-F64_ONLY, LOWP_ONLY = (8, 9, 10), (6, 7)
+F64_ONLY, LOWP_ONLY = (8, 9, 10, 11, 12), (6, 7)
 
 
-@pytest.mark.parametrize("cfg", range(11))
+@pytest.mark.parametrize("cfg", range(negf.N_CFG))
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_sigma2b_every_tile_config(ctx, torch_mod, cfg, dtype):
     """Every tile configuration the tuner can pick, on a size with several column

@@ -154,3 +154,28 @@ def test_bf16_slice_limit_checked_on_host(L):
     Gs = (C.c_void_p * 1)(16)
     rc = L.negf_sigma2b_batched(fake, 1, n, 70000, sg, ptrs, Gs, outs, negf.BF16, None)
     assert rc == negf.EINVAL and b"65535" in L.negf_last_error()
+
+
+def test_harmonic_trap_setup_matches_oracle(L):
+    s = W.harmonic_trap(n_elec=20.0, omega=0.8, half_width=10.0, n_e=21, n_g=5)
+    x, Wt, T, v, V = negf.fedvr_build_system(s)
+    st = fedvr.Setup(s)
+    assert np.max(np.abs(v - st.v)) < 1e-13 * np.max(np.abs(st.v))
+    assert np.max(np.abs(V - st.V)) < 1e-13
+    with pytest.raises(negf.NegfError):
+        negf.fedvr_build(s.bounds, s.n_g, [], [], omega=-1.0)
+
+
+def test_density_at_matches_oracle(L):
+    from oracle import observables as O, hf as H
+    s = W.config_he()
+    st = fedvr.Setup(s)
+    r = H.hartree_fock(st.h, st.V, 2.0, 2, s.beta)
+    xs = np.concatenate([np.linspace(-10.5, 10.5, 57), st.x, st.grid.bounds])
+    got = negf.density_at(s.bounds, s.n_g, r.rho, 2, xs)
+    inside = (xs >= s.bounds[0]) & (xs <= s.bounds[-1])
+    ref = O.density_at(st.grid, r.rho, 2, xs[inside])
+    assert np.max(np.abs(got[inside] - ref)) < 1e-12 * np.max(ref)
+    assert np.all(got[~inside] == 0.0)
+    with pytest.raises(negf.NegfError):
+        negf.density_at(s.bounds, s.n_g, r.rho, 3, xs)

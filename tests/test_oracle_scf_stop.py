@@ -61,17 +61,17 @@ def test_contraction_stop_is_within_tol_of_the_converged_energy(he):
 
 
 def test_guard_restarts_a_start_with_the_wrong_electron_count(he):
-    """A start holding half the electrons (N = 1 instead of 2) is replaced by G0
-    with alpha halved: the result is the HF-started run at alpha / 2, one
+    """A start holding a quarter of the electrons (N = 0.5 instead of 2) is replaced
+    by G0 with alpha halved: the result is the HF-started run at alpha / 2, one
     wasted step ahead of it."""
     setup, hf, G0 = SC.hf_start(he)
     half = SC.scf(he, alpha=0.15, tol=1e-10, setup=setup, hf=hf)
-    r = SC.scf(he, alpha=0.3, tol=1e-10, G_init=0.5 * G0, guard=True, setup=setup, hf=hf)
+    r = SC.scf(he, alpha=0.3, tol=1e-10, G_init=0.25 * G0, guard=True, setup=setup, hf=hf)
     assert r.backoffs == 1 and r.alpha == 0.15 and r.wasted == 1
     assert r.iters == half.iters + 1
     assert np.max(np.abs(r.G - half.G)) == 0.0 and r.E == half.E
     # without the guard the wrong start is iterated as given
-    u = SC.scf(he, alpha=0.3, tol=1e-10, G_init=0.5 * G0, fixed_iters=2, setup=setup, hf=hf)
+    u = SC.scf(he, alpha=0.3, tol=1e-10, G_init=0.25 * G0, fixed_iters=2, setup=setup, hf=hf)
     assert abs(u.energies[0] - half.energies[0]) > 0.1
 
 
@@ -81,6 +81,6 @@ def test_guard_gives_up_after_three_restarts(he):
     halvings and is then iterated with alpha / 8."""
     sysd = he.with_(n_elec=2.0)
     setup, hf, G0 = SC.hf_start(sysd)
-    bad = sysd.with_(n_elec=3.0)          # the guard compares N with 3, the state holds 2
+    bad = sysd.with_(n_elec=6.0)          # the guard compares N with 6, the state holds 2
     r = SC.scf(bad, alpha=0.4, tol=1e-8, guard=True, setup=setup, hf=hf, max_iter=3)
     assert r.backoffs == 3 and r.alpha == 0.05 and r.wasted == 3
