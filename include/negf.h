@@ -200,6 +200,25 @@ int negf_density_at(const negf_grid_t* grid, const double* rho, int sigma, int n
 int negf_sigma2b(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
                  const void* G, void* Sigma_c, int dtype, void* stream);
 
+/* Largest n_tau accepted by negf_sigma2b_noalloc. */
+#define NEGF_SIGMA2B_NOALLOC_MAX_TAU 65536
+
+/* negf_sigma2b for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that forbid hipMalloc): the same kernels and
+ * the same tile configuration as negf_sigma2b, so the same results, but no
+ * allocation of any kind. The per-slice exponents of NEGF_F32 go to a fixed
+ * device array of NEGF_SIGMA2B_NOALLOC_MAX_TAU ints (256 KiB) that the library
+ * holds on every GPU it runs on until the process ends; negf_ctx_create takes
+ * its address for the context's device. NEGF_F64 needs no scratch. Every call
+ * on one GPU shares that array and overwrites it completely before use, so
+ * calls that overlap on one GPU (different streams, different host threads)
+ * race and must not be issued. Arguments as for negf_sigma2b; the context's
+ * tuned configuration (negf_sigma2b_tune / _set_config) is used if present.
+ * Errors: as negf_sigma2b, plus NEGF_EINVAL for n_tau above the limit and for
+ * NEGF_BF16 (its slice copy is too large for a fixed array). */
+int negf_sigma2b_noalloc(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V,
+                         const void* G, void* Sigma_c, int dtype, void* stream);
+
 /* Autotuner for negf_sigma2b: times each of its tile configurations (values of i
  * per workgroup x column-chunk width) on the given input and stores the fastest
  * for (dtype, n_b) in the context; later negf_sigma2b calls with that dtype and

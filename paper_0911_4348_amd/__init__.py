@@ -97,6 +97,7 @@ _SIGS = {
     "negf_g0_build": (C.c_int, [_VP, C.c_int, C.c_int, _DP, C.c_double, _VP, _VP, C.c_double, _VP,
                                 C.c_int, _VP]),
     "negf_sigma2b": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _VP]),
+    "negf_sigma2b_noalloc": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _VP]),
     "negf_sigma2b_tune": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP, C.c_int, _IP, _DP, _VP]),
     "negf_sigma2b_set_config": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int]),
     "negf_dyson_step": (C.c_int, [_VP, C.POINTER(TauGridT), C.c_int, C.c_int, _VP, _VP, _VP, _VP,
@@ -355,6 +356,15 @@ def sigma2b(ctx: Context, V, G, sigma: int, dtype="f64", out=None, stream=None):
         out = torch.empty_like(G)
     _check(lib().negf_sigma2b(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
                               _DT[dtype], _stream(stream)))
+    return out
+
+
+def sigma2b_noalloc(ctx: Context, V, G, sigma: int, out, dtype="f64", stream=None):
+    """negf_sigma2b_noalloc: Sigma_c into the caller's ``out`` (same shape as G);
+    float64 or float32 only, no allocation by the library or by this wrapper."""
+    n_tau, n, _ = G.shape
+    _check(lib().negf_sigma2b_noalloc(ctx.handle, n, n_tau, int(sigma), _dev_ptr(V), _dev_ptr(G), _dev_ptr(out),
+                                      _DT[dtype], _stream(stream)))
     return out
 
 

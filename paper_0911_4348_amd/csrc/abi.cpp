@@ -121,6 +121,13 @@ extern "C" int negf_ctx_create(int device, negf_ctx** out) {
         set_error("device %d out of range (%d devices)", device, n);
         return NEGF_ENODEV;
     }
+    // address of this device's copy of the allocation-free Sigma-2B array
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    HIP_TRY(hipSetDevice(device));
+    const int irc = s2b_noalloc_init(device);
+    (void)hipSetDevice(cur);
+    NEGF_TRY(irc);
     negf_ctx* c = new negf_ctx();
     c->device = device;
     *out = c;
@@ -466,6 +473,25 @@ extern "C" int negf_density(negf_ctx* ctx, int n_b, int n_tau, int sigma, const 
     NEGF_TRY(bind_device(ctx));
     if (dtype == NEGF_F64) return density_run<double>(n_b, n_tau, sigma, W, (const double*)G, n, (hipStream_t)stream);
     return density_run<float>(n_b, n_tau, sigma, W, (const float*)G, n, (hipStream_t)stream);
+}
+
+extern "C" int negf_sigma2b_noalloc(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V, const void* G,
+                                    void* Sc, int dtype, void* stream) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(n_b >= 1 && n_b <= 4096, "n_b = %d out of range [1, 4096]", n_b);
+    NEGF_REQUIRE(n_tau >= 2 && n_tau <= NEGF_SIGMA2B_NOALLOC_MAX_TAU,
+                 "n_tau = %d out of range [2, %d] for the allocation-free entry", n_tau, NEGF_SIGMA2B_NOALLOC_MAX_TAU);
+    NEGF_REQUIRE(sigma == 1 || sigma == 2, "sigma must be 1 or 2");
+    NEGF_REQUIRE(V && G && Sc, "NULL buffer");
+    NEGF_REQUIRE(G != Sc, "Sigma_c must not alias G");
+    NEGF_REQUIRE(dtype == NEGF_F64 || dtype == NEGF_F32,
+                 "dtype %d: the allocation-free entry takes NEGF_F64 or NEGF_F32 (bf16 needs a slice copy)", dtype);
+    NEGF_TRY(bind_device(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == NEGF_F64)
+        return sigma2b_run_noalloc<double>(ctx, n_b, n_tau, sigma, (const double*)V, (const double*)G, (double*)Sc,
+                                           st);
+    return sigma2b_run_noalloc<float>(ctx, n_b, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, st);
 }
 
 extern "C" int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* V, const void* G,

@@ -106,6 +106,12 @@ template <class T>
 int sigma2b_run(negf_ctx* ctx, int n_b, int n_tau, int sigma, const T* V, const T* G,
                 T* Sc, bool bf16, hipStream_t st);
 int sigma2b_set_cfg(negf_ctx* ctx, int dtype, int n_b, int cfg);
+// Allocation-free form (float64 / float32): the float32 slice exponents go to a
+// fixed per-device array whose address s2b_noalloc_init (device current) records.
+int s2b_noalloc_init(int device);
+template <class T>
+int sigma2b_run_noalloc(negf_ctx* ctx, int n_b, int n_tau, int sigma, const T* V, const T* G, T* Sc,
+                        hipStream_t st);
 template <class T>
 int sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const T* V, const T* G, T* Sc,
                  bool bf16, int* best, double* ms, hipStream_t st);

@@ -24,6 +24,7 @@
 // of small slices stay in range; only the stored float32 result can underflow.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 #include <type_traits>
@@ -1420,6 +1421,49 @@ int sigma2b_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T*
     return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st, ex_fixed);
 }
 
+// ---------------------------------------------------------------- allocation-free entry
+// The per-slice exponents of the float32 mode live in a fixed device array for
+// callers that cannot allocate (one copy per GPU, kept until the process ends).
+// Host code never passes the array's name to a kernel: each device's address
+// comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) int s2b_noalloc_ex[NEGF_SIGMA2B_NOALLOC_MAX_TAU];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::vector<int*> g_noalloc_ptr;      // per device id
+}  // namespace
+
+int s2b_noalloc_init(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if ((int)g_noalloc_ptr.size() <= device) g_noalloc_ptr.resize(device + 1, nullptr);
+    if (g_noalloc_ptr[device]) return NEGF_OK;
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(s2b_noalloc_ex)));
+    g_noalloc_ptr[device] = static_cast<int*>(p);
+    return NEGF_OK;
+}
+
+template <class T>
+int sigma2b_run_noalloc(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T* G, T* Sc, hipStream_t st) {
+    int* ex = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (ctx->device < (int)g_noalloc_ptr.size()) ex = g_noalloc_ptr[ctx->device];
+    }
+    if (!ex) {
+        set_error("allocation-free Sigma-2B: device %d was not set up by negf_ctx_create", ctx->device);
+        return NEGF_EHIP;
+    }
+    const int mode = sizeof(T) == 8 ? MODE_F64 : MODE_F32;
+    auto it = ctx->filled.find(tune_key(mode, n));
+    int cfg = it != ctx->filled.end() ? it->second : default_cfg(mode, n);
+    // the configurations that stage through padded copies need scratch: the
+    // 208-column matrix-core tile stands in for them
+    if (cfg >= 11) cfg = 0;
+    return sigma2b_cfg<T>(ctx, n, n_tau, sigma, V, G, Sc, false, cfg, st, ex);
+}
+template int sigma2b_run_noalloc<double>(negf_ctx*, int, int, int, const double*, const double*, double*, hipStream_t);
+template int sigma2b_run_noalloc<float>(negf_ctx*, int, int, int, const float*, const float*, float*, hipStream_t);
 
 // Time every tile configuration on the caller's input (after one untimed
 // launch each) and remember the fastest for (mode, n_b) in the context.

@@ -179,3 +179,12 @@ def test_density_at_matches_oracle(L):
     assert np.all(got[~inside] == 0.0)
     with pytest.raises(negf.NegfError):
         negf.density_at(s.bounds, s.n_g, r.rho, 3, xs)
+
+
+def test_noalloc_rejects_on_the_host(L):
+    """The allocation-free Sigma-2B entry checks its limits before touching a device."""
+    p = C.c_void_p(8)
+    rc = L.negf_sigma2b_noalloc(C.c_void_p(1), 8, 65537, 2, p, C.c_void_p(16), C.c_void_p(24), negf.F32, None)
+    assert rc == negf.EINVAL and b"allocation-free" in L.negf_last_error()
+    rc = L.negf_sigma2b_noalloc(C.c_void_p(1), 8, 5, 2, p, C.c_void_p(16), C.c_void_p(24), negf.BF16, None)
+    assert rc == negf.EINVAL and b"bf16" in L.negf_last_error()
