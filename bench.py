@@ -103,42 +103,40 @@ def cpu_baseline(V, G, sigma, target_s=15.0):
 
 def scf_compare(torch, negf, W, seed=100000):
     """Time to 1e-6 Ha for one held-out random potential on the n_b = 199 grid (1025 tau points,
-    beta = 50): plain float64 from the HF start, the mixed forms (float32 loop, bf16 Sigma-2B loop; float64
-    refinement) and the learned start. Every run continues to |dE| < 1e-8 Ha; E_ref is the plain run's final
-    energy. Reported per run: steps and wall time (HF and set-up included) until |E_k - E_ref| < 1e-6 Ha,
-    and until the stopping rule |E_k - E_(k-1)| < 1e-6 Ha first holds."""
+    beta = 50), by the library's own contraction-aware stopping rule (it bounds |E - E_inf| for a
+    geometric tail): plain float64 from the HF start, the mixed forms (float32 loop, bf16 Sigma-2B
+    loop; float64 refinement) and the learned start. E_ref comes from the plain run continued to a
+    1e-10 Ha bound; every run reports its steps, its wall time (HF and set-up included) and its
+    final |E - E_ref|."""
     from paper_0911_4348_amd import learned_guess as LG
     s = W.random_potential_system(seed)
     ctx = negf.Context(0)
-    kw = dict(conv=negf.CONV_FFT, want_G=False, max_iter=400)
+    kw = dict(conv=negf.CONV_FFT, want_G=False, max_iter=400, stop="contraction", guard=True)
     negf.scf(ctx, s, fixed_iters=1, dtype="bf16", **kw)         # kernel loading outside the timed runs
-    runs = {"plain_f64": dict(tol=1e-8), "mixed_f32": dict(tol=1e-6, dtype="f32", refine_tol=1e-8),
-            "mixed_bf16": dict(tol=1e-6, dtype="bf16", refine_tol=1e-8)}
+    E_ref = negf.scf(ctx, s, tol=1e-10, **kw).E
+    runs = {"plain_f64": dict(tol=1e-6), "mixed_f32": dict(tol=1e-5, dtype="f32", refine_tol=1e-6),
+            "mixed_bf16": dict(tol=1e-5, dtype="bf16", refine_tol=1e-6)}
     if os.path.exists(LG.WEIGHTS):
         p, scale, _ = LG.load()
         params = torch.from_numpy(p).cuda()
-        runs["learned_f64"] = dict(tol=1e-8, guess=params, guess_scale=scale)
-        runs["learned_mixed_bf16"] = dict(tol=1e-6, dtype="bf16", refine_tol=1e-8, guess=params, guess_scale=scale)
-    out, E_ref = {}, None
+        runs["learned_f64"] = dict(tol=1e-6, guess=params, guess_scale=scale)
+        runs["learned_mixed_bf16"] = dict(tol=1e-5, dtype="bf16", refine_tol=1e-6, guess=params, guess_scale=scale)
+    out = {}
     for name, o in runs.items():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = negf.scf(ctx, s, **kw, **o)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        if E_ref is None:
-            E_ref = r.E
-        k_acc, t_acc, _ = LG._time_to(r.log, wall, 1e-6, E_ref)
-        k_rule, t_rule, E_rule = LG._time_to(r.log, wall, 1e-6)
-        out[name] = {"steps_to_1e-6": k_acc, "s_to_1e-6": round(t_acc, 3), "steps_to_rule": k_rule,
-                     "s_to_rule": round(t_rule, 3), "abs_err_at_rule_Ha": float(abs(E_rule - E_ref)),
-                     "final_abs_err_Ha": float(abs(r.E - E_ref))}
-    base = out["plain_f64"]["s_to_1e-6"]
+        out[name] = {"steps": r.iters, "s": round(wall, 3), "abs_err_Ha": float(abs(r.E - E_ref)),
+                     "low_precision_steps": sum(1 for q in r.log if q["dtype"] != negf.F64), "status": r.status}
+    base = out["plain_f64"]["s"]
     for v in out.values():
-        v["speedup_vs_plain_f64"] = round(base / v["s_to_1e-6"], 3)
+        v["speedup_vs_plain_f64"] = round(base / v["s"], 3)
     ctx.close()
     return {"workload": f"random soft-Coulomb potential seed {seed} (held out), n_b = 199, 1025 tau points, "
-                        f"beta = 50, alpha = 0.3, HF and set-up included",
+                        f"beta = 50, alpha = 0.3, runaway guard, contraction-aware stop at 1e-6 Ha (mixed: "
+                        f"1e-5 in low precision, then float64 to 1e-6), HF and set-up included",
             "E_ref": E_ref, "runs": out}
 
 
@@ -198,7 +196,7 @@ def run_paper(args, torch, negf, W):
     res = {}
     ctx = negf.Context(0)
     he = W.he_1d(bounds=W.graded_bounds(100.0, 29), n_g=7, beta=100.0)
-    meshes = [(int(u), int(p)) for u, p in (m.split("x") for m in args.paper_meshes.split(","))]
+    meshes = [(int(u), int(p)) for u, p in (m.split("x") for m in args.paper_meshes.split(",") if m)]
     he_runs = []
     for u, pw in meshes:
         s = he.with_(tau_kind="power", u=u, p=pw)
@@ -208,14 +206,15 @@ def run_paper(args, torch, negf, W):
         dt = time.perf_counter() - t0
         he_runs.append({"u": u, "p": pw, "n_tau": s.n_tau, "E_2B": r.E, "E_HF": r.hf_E, "N": r.N, "steps": r.iters,
                         "status": r.status, "s": round(dt, 2)})
-        print(f"He case II u={u} p={pw} ({s.n_tau} points): E_2B = {r.E:.8f}, N = {r.N:.6f}, {r.iters} steps, "
-              f"{dt:.1f} s", file=sys.stderr, flush=True)
+        print(f"He case II u={u} p={pw} ({s.n_tau} points): E_HF = {r.hf_E:.8f}, E_2B = {r.E:.8f}, N = {r.N:.6f}, "
+              f"{r.iters} steps, {dt:.1f} s", file=sys.stderr, flush=True)
     E_exact = -2.2382578
-    best = he_runs[-1]
-    res["he_case2"] = {"n_b": he.n_b, "beta": he.beta, "runs": he_runs, "paper_E_HF": -2.2242096,
-                       "paper_E_2B": -2.233419, "paper_E_exact": E_exact,
-                       "correlation_fraction": (best["E_2B"] - best["E_HF"]) / (E_exact - best["E_HF"]),
-                       "paper_correlation_fraction": 0.66}
+    if he_runs:
+        best = he_runs[-1]
+        res["he_case2"] = {"n_b": he.n_b, "beta": he.beta, "runs": he_runs, "paper_E_HF": -2.2242096,
+                           "paper_E_2B": -2.233419, "paper_E_exact": E_exact,
+                           "correlation_fraction": (best["E_2B"] - best["E_HF"]) / (E_exact - best["E_HF"]),
+                           "paper_correlation_fraction": 0.66}
     # H3+ bond-length scan on the case-II 50 a.u. grid
     Rs = np.round(np.arange(args.paper_rmin, args.paper_rmax + 1e-9, args.paper_rstep), 6)
     base = W.h3p_1d(R=2.2, bounds=W.graded_bounds(25.0, 13), n_g=11, beta=100.0, tau_kind="power",
@@ -223,7 +222,7 @@ def run_paper(args, torch, negf, W):
     systems = [base.with_(centres=np.array([-R, 0.0, R]), e_nn=5.0 / (2.0 * R)) for R in Rs]
     t0 = time.perf_counter()
     outs = negf.scf_batched(ctx, systems, tol=1e-8, stop="contraction", guard=True, want_G=False, max_iter=400,
-                            allow_noconv=True, dtype=args.dtype, refine_tol=1e-8)
+                            allow_noconv=True, dtype=args.dtype, refine_tol=1e-8, progress=True)
     dt = time.perf_counter() - t0
     E2 = np.array([o.E for o in outs])
     E1 = np.array([o.hf_E for o in outs])
@@ -243,7 +242,7 @@ def run_paper(args, torch, negf, W):
     print(f"H3+ case II: R_eq HF {R_hf:.4f} (paper {4.3654 / 2:.4f}), 2B {R_2b:.4f} (paper {4.5579 / 2:.4f}), "
           f"{dt:.1f} s", file=sys.stderr, flush=True)
     out = {"metric": "paper-grid validation (energies and equilibrium distances against the paper's printed values)",
-           "value": res["he_case2"]["runs"][-1]["E_2B"], "unit": "Ha", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "value": res["he_case2"]["runs"][-1]["E_2B"] if he_runs else res["h3p_case2"]["E_min_2B"], "unit": "Ha", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": args.dtype, "data": "synthetic",
            "config": {"workload": "1D He case-II grid (29 x 8 GLL, n_b 202, beta 100, power meshes) and linear "

@@ -244,7 +244,7 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
 /* Sustained rate of the matrix-core operation the Sigma-2B kernels issue for
- * `dtype` (NEGF_F64: 16x16x4 float64, NEGF_F32: 16x16x4 float32, NEGF_BF16:
+ * `dtype` (NEGF_F64: four-block 4x4x4 float64, NEGF_F32: 16x16x4 float32, NEGF_BF16:
  * 16x16x32 bf16 with float32 accumulation), measured on the context's GPU: a
  * kernel of 8 independent accumulator chains per wave with register operands,
  * 8 waves per SIMD on every compute unit, run twice (the faster run counts).

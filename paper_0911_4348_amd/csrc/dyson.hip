@@ -367,9 +367,10 @@ __global__ __launch_bounds__(512) void k_conv_strip(int n, int n_tau, int kind, 
 #pragma unroll
                 for (int ks = 0; ks < BK / 4; ++ks) {
                     const int kk = ks * 4 + (lane >> 4);
-                    const T a = As[kk][rt * 16 + (lane & 15)];
+                    AFrag<T> a;
+                    a.load(lane, [&](int m) { return As[kk][rt * 16 + m]; });
 #pragma unroll
-                    for (int t = 0; t < JTW; ++t) acc[t] = Mma<T>::mma(a, Bs[kk][(cg + 2 * t) * 16 + (lane & 15)], acc[t]);
+                    for (int t = 0; t < JTW; ++t) acc[t] = a.mma(Bs[kk][(cg + 2 * t) * 16 + (lane & 15)], acc[t]);
                 }
                 __syncthreads();
             }
@@ -528,6 +529,117 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
                     const double R = c * (acc + hR[p] * b);
                     if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b);
                     Out[(long)p * nn + e] = (T)(-L + R - c * Eb[(long)p * n + k] * cjk);
+                }
+            }
+        }
+    }
+}
+
+// The same recurrences with In read once and Out written once: the tau axis is
+// cut into 32 chunks of at most CL points, a workgroup holds 16 elements x 32
+// chunks, and each thread keeps its chunk of In and of the forward results in
+// registers. Both aggregates (forward and backward) come from one pass over the
+// registers, are folded in LDS, and the forward and backward output sweeps run
+// over the registers; only the final values are stored. Needs n_tau <= 32 CL.
+template <class T, int CL>
+__global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T* __restrict__ In, T* __restrict__ Out,
+                                                      const double* __restrict__ w, const double* __restrict__ hL,
+                                                      const double* __restrict__ hR, const double* __restrict__ Ea,
+                                                      const double* __restrict__ Eb, const double* __restrict__ dec,
+                                                      const double* __restrict__ cpre,
+                                                      const double* __restrict__ eps, double mu,
+                                                      const double* __restrict__ C) {
+    constexpr int NCH = 32, NE = 16;
+    __shared__ double sdf[NCH][NE + 1], saf[NCH][NE + 1], sdb[NCH][NE + 1], sab[NCH][NE + 1];
+    const int el = threadIdx.x & (NE - 1), ch = threadIdx.x / NE;
+    const long nn = (long)n * n;
+    const long e = (long)blockIdx.x * NE + el;
+    const bool ok = e < nn;
+    const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
+    const bool pos = ok && eps[k] - mu >= 0.0;
+    const double c = ok ? cpre[k] : 0.0;
+    const int M = n_tau - 1, P = n_tau;
+    const int p0 = (int)((long)ch * P / NCH), p1 = (int)((long)(ch + 1) * P / NCH);
+    double b[CL], L[CL];
+#pragma unroll
+    for (int t = 0; t < CL; ++t) b[t] = (ok && p0 + t < p1) ? (double)In[(long)(p0 + t) * nn + e] : 0.0;
+    // chunk aggregates: acc_out = d acc_in + a, forward (increasing p) and backward
+    {
+        double af = 0.0, df = 1.0, ab = 0.0, db = 1.0;
+        if (ok) {
+#pragma unroll
+            for (int t = 0; t < CL; ++t) {
+                const int p = p0 + t;
+                if (p < p1) {
+                    if (pos) {
+                        if (p < M) {
+                            const double dp = dec[(long)p * n + k];
+                            af = dp * (af + w[p] * b[t]);
+                            df *= dp;
+                        }
+                    } else {
+                        af += w[p] * Ea[(long)p * n + k] * b[t];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = CL - 1; t >= 0; --t) {
+                const int p = p0 + t;
+                if (p < p1) {
+                    if (pos) {
+                        ab += w[p] * Eb[(long)p * n + k] * b[t];
+                    } else if (p > 0) {
+                        const double dp = dec[(long)(p - 1) * n + k];
+                        ab = dp * (ab + w[p] * b[t]);
+                        db *= dp;
+                    }
+                }
+            }
+        }
+        sdf[ch][el] = df;
+        saf[ch][el] = af;
+        sdb[ch][el] = db;
+        sab[ch][el] = ab;
+    }
+    __syncthreads();
+    if (!ok) return;
+    // forward sweep (lower part of the convolution)
+    {
+        double acc = 0.0;
+        for (int cc = 0; cc < ch; ++cc) acc = sdf[cc][el] * acc + saf[cc][el];
+#pragma unroll
+        for (int t = 0; t < CL; ++t) {
+            const int p = p0 + t;
+            if (p < p1) {
+                if (pos) {
+                    L[t] = c * (acc + hL[p] * b[t]);
+                    if (p < M) acc = dec[(long)p * n + k] * (acc + w[p] * b[t]);
+                } else {
+                    const double ea = Ea[(long)p * n + k];
+                    L[t] = c * Eb[(long)p * n + k] * (acc + hL[p] * ea * b[t]);
+                    acc += w[p] * ea * b[t];
+                }
+            }
+        }
+    }
+    // backward sweep (upper part), combined with the forward result
+    {
+        double acc = 0.0;
+        for (int cc = NCH - 1; cc > ch; --cc) acc = sdb[cc][el] * acc + sab[cc][el];
+        const double cjk = C[(long)j * n + k];
+#pragma unroll
+        for (int t = CL - 1; t >= 0; --t) {
+            const int p = p0 + t;
+            if (p < p1) {
+                if (pos) {
+                    const double eb = Eb[(long)p * n + k], ea = Ea[(long)p * n + k];
+                    const double R = c * ea * (acc + hR[p] * eb * b[t]);
+                    acc += w[p] * eb * b[t];
+                    Out[(long)p * nn + e] = (T)(-L[t] + R - c * ea * cjk);
+                } else {
+                    const double R = c * (acc + hR[p] * b[t]);
+                    if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b[t]);
+                    Out[(long)p * nn + e] = (T)(-L[t] + R - c * Eb[(long)p * n + k] * cjk);
                 }
             }
         }
@@ -806,8 +918,18 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
     hipLaunchKernelGGL(k_scan_tables, dim3(grid_for((long)n * n_tau)), dim3(256), 0, st, n, n_tau, d_tau, tg->beta,
                        eps, mu, Ea, Eb, dec, cpre);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_eig_scan_chunked<T>), dim3((unsigned)((nn + 15) / 16)), dim3(256), 0, st, n, n_tau, It, I1,
-                       d_w, d_hL, d_hR, Ea, Eb, dec, cpre, eps, mu, C);
+    // G0 + Q[G0, I1] in the eigenbasis: In read once and Out written once where a
+    // chunk of 32 fits in registers, else the chunked kernel that rereads In
+    const unsigned sblk = (unsigned)((nn + 15) / 16);
+    if (n_tau <= 32 * 17)
+        hipLaunchKernelGGL((k_eig_scan_reg<T, 17>), dim3(sblk), dim3(512), 0, st, n, n_tau, It, I1, d_w, d_hL, d_hR, Ea,
+                           Eb, dec, cpre, eps, mu, C);
+    else if (n_tau <= 32 * 33)
+        hipLaunchKernelGGL((k_eig_scan_reg<T, 33>), dim3(sblk), dim3(512), 0, st, n, n_tau, It, I1, d_w, d_hL, d_hR, Ea,
+                           Eb, dec, cpre, eps, mu, C);
+    else
+        hipLaunchKernelGGL((k_eig_scan_chunked<T>), dim3(sblk), dim3(256), 0, st, n, n_tau, It, I1, d_w, d_hL, d_hR,
+                           Ea, Eb, dec, cpre, eps, mu, C);
     LAUNCH_CHECK();
     NEGF_TRY(gemm<T>(st, false, false, n, n, n, (T)alpha, Ct, n, 0, I1, n, nn, (T)(1.0 - alpha), G_in, n, nn, G_out,
                      n, nn, n_tau));

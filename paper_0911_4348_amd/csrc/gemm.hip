@@ -100,14 +100,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            T a0 = As[buf][kk][wr * 32 + (lane & 15)];
-            T a1 = As[buf][kk][wr * 32 + 16 + (lane & 15)];
+            AFrag<T> a0, a1;
+            a0.load(lane, [&](int m) { return As[buf][kk][wr * 32 + m]; });
+            a1.load(lane, [&](int m) { return As[buf][kk][wr * 32 + 16 + m]; });
             T b0 = Bs[buf][kk][wc * 32 + (lane & 15)];
             T b1 = Bs[buf][kk][wc * 32 + 16 + (lane & 15)];
-            acc[0][0] = Mma<T>::mma(a0, b0, acc[0][0]);
-            acc[0][1] = Mma<T>::mma(a0, b1, acc[0][1]);
-            acc[1][0] = Mma<T>::mma(a1, b0, acc[1][0]);
-            acc[1][1] = Mma<T>::mma(a1, b1, acc[1][1]);
+            acc[0][0] = a0.mma(b0, acc[0][0]);
+            acc[0][1] = a0.mma(b1, acc[0][1]);
+            acc[1][0] = a1.mma(b0, acc[1][0]);
+            acc[1][1] = a1.mma(b1, acc[1][1]);
         }
         // the other buffer was last read before the previous barrier
         if (more) store(buf ^ 1);
@@ -189,11 +190,13 @@ __global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, 
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            T ar[2], ai[2], br[2], bi[2];
+            AFrag<T> ar[2], ai[2], nai[2];
+            T br[2], bi[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                ar[h] = Asr[buf][kk][wr * 32 + 16 * h + (lane & 15)];
-                ai[h] = Asi[buf][kk][wr * 32 + 16 * h + (lane & 15)];
+                ar[h].load(lane, [&](int m) { return Asr[buf][kk][wr * 32 + 16 * h + m]; });
+                ai[h].load(lane, [&](int m) { return Asi[buf][kk][wr * 32 + 16 * h + m]; });
+                nai[h] = ai[h].neg();
                 br[h] = Bsr[buf][kk][wc * 32 + 16 * h + (lane & 15)];
                 bi[h] = Bsi[buf][kk][wc * 32 + 16 * h + (lane & 15)];
             }
@@ -201,10 +204,10 @@ __global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, 
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    cr[i][j] = Mma<T>::mma(ar[i], br[j], cr[i][j]);
-                    cr[i][j] = Mma<T>::mma(-ai[i], bi[j], cr[i][j]);
-                    ci[i][j] = Mma<T>::mma(ar[i], bi[j], ci[i][j]);
-                    ci[i][j] = Mma<T>::mma(ai[i], br[j], ci[i][j]);
+                    cr[i][j] = ar[i].mma(br[j], cr[i][j]);
+                    cr[i][j] = nai[i].mma(bi[j], cr[i][j]);
+                    ci[i][j] = ar[i].mma(bi[j], ci[i][j]);
+                    ci[i][j] = ai[i].mma(br[j], ci[i][j]);
                 }
         }
         if (more) store(buf ^ 1);

@@ -37,6 +37,46 @@ struct Mma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// A operand of one 16 x 16 x 4 product, and the product itself, in the form
+// each dtype runs fastest on gfx950. float32: the 16x16x4 shape, one value per
+// lane, A[lane % 16][lane / 16]. float64: four four-block 4x4x4 products (rows
+// 4r .. 4r+3 of the tile), which sustain about 1.5x the rate of the 16x16x4
+// shape; with the same A rows in all four blocks, block b holds columns
+// 4b .. 4b+3, so B and the result keep the 16x16x4 lanes and registers, and A
+// needs A[4r + lane % 4][lane / 16] for r < 4. load(row) returns A[row][lane / 16].
+template <class T>
+struct AFrag;
+
+template <>
+struct AFrag<double> {
+    double v[4];
+    template <class F>
+    __device__ __forceinline__ void load(int lane, F row) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = row(4 * r + (lane & 3));
+    }
+    __device__ __forceinline__ dv4 mma(double b, dv4 c) const {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = __builtin_amdgcn_mfma_f64_4x4x4f64(v[r], b, c[r], 0, 0, 0);
+        return c;
+    }
+    __device__ __forceinline__ AFrag neg() const {
+        AFrag o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o.v[r] = -v[r];
+        return o;
+    }
+};
+
+template <>
+struct AFrag<float> {
+    float v;
+    template <class F>
+    __device__ __forceinline__ void load(int lane, F row) { v = row(lane & 15); }
+    __device__ __forceinline__ fv4 mma(float b, fv4 c) const { return Mma<float>::mma(v, b, c); }
+    __device__ __forceinline__ AFrag neg() const { return AFrag{-v}; }
+};
+
 // Sum over the 16 lanes that share lane / 16 (lane bits 0-3).
 template <class T>
 __device__ __forceinline__ T sum16(T v) {

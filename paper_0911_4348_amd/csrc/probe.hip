@@ -1,8 +1,9 @@
-// Sustained matrix-core rate of the MFMA shapes the Sigma-2B kernels issue,
-// measured on the device at hand: a ceiling for the roofline comparison beside
-// the datasheet figure. Every wave runs 8 independent accumulator chains of one
-// MFMA shape with register operands (no memory traffic in the loop), 8 waves per
-// SIMD on every compute unit. Each wave also reads the core-clock counter
+// Measurement helper, not part of the method: sustained matrix-core rate of the
+// MFMA shapes the Sigma-2B kernels issue, measured on the device at hand, a
+// ceiling for the roofline comparison beside the datasheet figure. Every wave
+// runs 8 independent accumulator chains of one MFMA shape with register
+// operands (no memory traffic in the loop), 8 waves per SIMD on every compute
+// unit. Each wave also reads the core-clock counter
 // (s_memtime) and the fixed-rate counter (s_memrealtime) around its loop, which
 // gives the shader clock the loop ran at.
 #include <algorithm>
@@ -13,7 +14,6 @@
 namespace negf {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
@@ -23,19 +23,24 @@ constexpr int kBlocksPerCU = 8;
 
 template <int MODE>
 struct Shape;
+// float64: the four-block 4x4x4 shape the float64 Sigma-2B tiles issue
 template <>
 struct Shape<NEGF_F64> {
-    typedef d4 acc_t;
-    static constexpr double flops = 2.0 * 16 * 16 * 4;
+    typedef double acc_t;
+    static constexpr double flops = 2.0 * 4 * 4 * 4 * 4;
+    static __device__ __forceinline__ acc_t zero() { return 0.0; }
+    static __device__ __forceinline__ double first(acc_t c) { return c; }
     static __device__ __forceinline__ acc_t step(acc_t c, int t) {
         const double a = t * 1e-3, b = 1.0 + t * 1e-4;
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
     }
 };
 template <>
 struct Shape<NEGF_F32> {
     typedef f4 acc_t;
     static constexpr double flops = 2.0 * 16 * 16 * 4;
+    static __device__ __forceinline__ acc_t zero() { return acc_t{0, 0, 0, 0}; }
+    static __device__ __forceinline__ double first(acc_t c) { return (double)c[0] + (double)c[3]; }
     static __device__ __forceinline__ acc_t step(acc_t c, int t) {
         const float a = t * 1e-3f, b = 1.0f + t * 1e-4f;
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -45,6 +50,8 @@ template <>
 struct Shape<NEGF_BF16> {
     typedef f4 acc_t;
     static constexpr double flops = 2.0 * 16 * 16 * 32;
+    static __device__ __forceinline__ acc_t zero() { return acc_t{0, 0, 0, 0}; }
+    static __device__ __forceinline__ double first(acc_t c) { return (double)c[0] + (double)c[3]; }
     static __device__ __forceinline__ acc_t step(acc_t c, int t) {
         bf8 a, b;
 #pragma unroll
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_matrix_rate(int iters, 
     const int t = threadIdx.x;
     acc_t acc[kChains];
 #pragma unroll
-    for (int j = 0; j < kChains; ++j) acc[j] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j < kChains; ++j) acc[j] = Shape<MODE>::zero();
     const unsigned long long c0 = __builtin_amdgcn_s_memtime();
     const unsigned long long r0 = __builtin_amdgcn_s_memrealtime();
     for (int it = 0; it < iters; ++it)
@@ -72,7 +79,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_matrix_rate(int iters, 
         for (int j = 0; j < kChains; ++j) acc[j] = Shape<MODE>::step(acc[j], t);
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < kChains; ++j) s += (double)acc[j][0] + (double)acc[j][3];
+    for (int j = 0; j < kChains; ++j) s += Shape<MODE>::first(acc[j]);
     const unsigned long long c1 = __builtin_amdgcn_s_memtime();
     const unsigned long long r1 = __builtin_amdgcn_s_memrealtime();
     out[(long)blockIdx.x * blockDim.x + t] = s;
@@ -137,7 +144,7 @@ int run(negf_ctx* ctx, int iters, double* tflops, double* ghz, hipStream_t st) {
 
 int matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* ghz, hipStream_t st) {
     switch (dtype) {
-        case NEGF_F64: return run<NEGF_F64>(ctx, 4000, tflops, ghz, st);
+        case NEGF_F64: return run<NEGF_F64>(ctx, 16000, tflops, ghz, st);
         case NEGF_F32: return run<NEGF_F32>(ctx, 8000, tflops, ghz, st);
         default: return run<NEGF_BF16>(ctx, 4000, tflops, ghz, st);
     }
