@@ -558,7 +558,7 @@ struct Layout {
     static constexpr int A_EL = 16 * 16;
     static constexpr int V_EL = IB * 16;             // V panel [IB][BK]
     static constexpr int STAGE_EL = B_EL + A_EL + V_EL;
-    static constexpr int VT_EL = 16 * JW;            // V tile of the epilogue [16][jw]
+    static constexpr int VT_EL = 16 * JW + IB * 16;  // V tile of the epilogue [16][jw], then G_il [IB][16]
     // one column chunk: the direct term is accumulated in the l-tile loop,
     // in a further [IB][np] array
     static size_t bytes(int np) {
@@ -571,6 +571,12 @@ struct Layout {
 __device__ __forceinline__ void load16(const double* g, double* lds_wave) {
     __builtin_amdgcn_global_load_lds(static_cast<const void*>(g), (__attribute__((address_space(3))) void*)lds_wave,
                                      16, 0, 0);
+}
+// The same from a wave-uniform base and a 32-bit per-lane byte offset, which
+// the instruction takes as a scalar base plus one vector register: the offsets
+// of a chunk then stay in one register each through the panel loop.
+__device__ __forceinline__ void load16(const double* base, unsigned byte_off, double* lds_wave) {
+    load16(reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off), lds_wave);
 }
 
 // Pieces 0 .. count-1 of a contiguous LDS region, piece c from src(c); the
@@ -603,6 +609,7 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
     const int npj = (np + JW - 1) / JW * JW;
     double* stage = smem;                            // [2][STAGE_EL]
     double* Vt = stage + 2 * L::STAGE_EL;            // [16][jw]
+    double* Gil = Vt + 16 * JW;                      // [IB][16]
     double* T1s = Vt + L::VT_EL;                     // [IB][np]
     double* Xs = T1s + IB * np;                      // [IB][np]
     double* XPs = Xs + IB * np;                      // [IB][np]
@@ -628,32 +635,40 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
         // is row c / (jw/2), columns 2 (c % (jw/2)) + 0, 1; A and V pieces as in
         // the panel layouts. A piece that does not exist gets -1.
         constexpr int NPB = (16 * (JW / 2) + NT - 1) / NT;      // B / V-tile pieces per lane
-        int offb[NPB];
+        // (byte offsets; ~0u marks a piece that does not exist)
+        constexpr unsigned kNone = ~0u;
+        unsigned offb[NPB];
         {
             const int hp = jw >> 1;
 #pragma unroll
             for (int t = 0; t < NPB; ++t) {
                 const int c = w * 64 + t * NT + lane;
                 const int kk = c / hp, jp = c - kk * hp;
-                offb[t] = c < 16 * hp ? kk * np + j0 + 2 * jp : -1;
+                offb[t] = c < 16 * hp ? 8u * (unsigned)(kk * np + j0 + 2 * jp) : kNone;
             }
         }
         const int ca = tid - (NT - 128);             // A pieces: the last two waves
-        const int offa = ca >= 0 ? (ca >> 3) * np + 2 * ((ca & 7) ^ ((ca >> 3) & 7)) : -1;
+        const unsigned offa = ca >= 0 ? 8u * (unsigned)((ca >> 3) * np + 2 * ((ca & 7) ^ ((ca >> 3) & 7))) : kNone;
+        const int cg = tid - 128;                    // G_il pieces of the epilogue: the third wave
         const int cv = tid - (NT - 192);             // V pieces: the wave before them
-        const int offv = (cv >= 0 && cv < IB * 8) ? (iblk * IB + (cv >> 3)) * np + 2 * (cv & 7) : -1;
-        // all 16 x jw pieces of a [16][jw] block of M (row stride np) into dst
-        auto copy_rows = [&](double* dst, const double* M) {
+        const unsigned offv =
+            (cv >= 0 && cv < IB * 8) ? 8u * (unsigned)((iblk * IB + (cv >> 3)) * np + 2 * (cv & 7)) : kNone;
+        // all 16 x jw pieces of the [16][jw] block of M (row stride np) that
+        // starts row0 rows down, into dst. The row offset is added to the 32-bit
+        // piece offsets (one slice is far below 4 GiB) and the base stays the
+        // slice pointer, so no 64-bit address is kept per piece across panels.
+        auto copy_rows = [&](double* dst, const double* M, int row0) {
+            const unsigned ro = 8u * (unsigned)(row0 * np);
 #pragma unroll
             for (int t = 0; t < NPB; ++t)
-                if (offb[t] >= 0) load16(M + offb[t], dst + 2 * (w * 64 + t * NT));
+                if (offb[t] != kNone) load16(M, offb[t] + ro, dst + 2 * (w * 64 + t * NT));
         };
         auto issue = [&](int l0, int pn, int buf) {
             double* sb = stage + buf * L::STAGE_EL;
             const int k0 = pn * BK;
-            copy_rows(sb, Gq + (long)k0 * np);
-            if (offa >= 0) load16(Gb + (long)l0 * np + k0 + offa, sb + L::B_EL + 2 * (ca & ~63));
-            if (offv >= 0) load16(Vp + k0 + offv, sb + L::B_EL + L::A_EL + 2 * (cv & ~63));
+            copy_rows(sb, Gq, k0);
+            if (offa != kNone) load16(Gb, offa + 8u * (unsigned)(l0 * np + k0), sb + L::B_EL + 2 * (ca & ~63));
+            if (offv != kNone) load16(Vp, offv + 8u * (unsigned)k0, sb + L::B_EL + L::A_EL + 2 * (cv & ~63));
         };
         int g = 0;                                   // panels started in this chunk
         issue(0, 0, 0);
@@ -661,10 +676,8 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
         __syncthreads();
         for (int l0 = 0; l0 < n; l0 += 16) {
             // V rows l0 .. l0+15 of this chunk for the epilogue; G_il for this wave's rows
-            copy_rows(Vt, Vp + (long)l0 * np);
-            double gil[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) gil[r] = Gq[(long)i * np + l0 + Mma<double>::row(lane, r)];
+            copy_rows(Vt, Vp, l0);
+            if (cg >= 0 && cg < IB * 8) load16(Gq, 8u * (unsigned)((iblk * IB + (cg >> 3)) * np + l0 + 2 * (cg & 7)), Gil);
             dv4 acc[JB];
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb) acc[jb] = Mma<double>::zero();
@@ -719,7 +732,9 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
                             if (Mma<double>::row(lane, r) == lc) T1s[w * np + l0 + lc] = acc[jb][r];
                     }
             }
-            double xp[4] = {0.0, 0.0, 0.0, 0.0};
+            double xp[4] = {0.0, 0.0, 0.0, 0.0}, gil[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gil[r] = Gil[w * 16 + Mma<double>::row(lane, r)];
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb) {
                 if (jb < njb) {

@@ -149,6 +149,17 @@ def test_sigma2b_microbench_sampled(ctx, torch_mod):
     for q in (0, 1, 300, 511, 512, 513, 1024):
         refs[q] = S.sigma2b_slice(V, G[q], G[s.M - q], 2)
         assert relerr(got[q], refs[q]) < TOL64, q
+    # float64 in the configuration the tuner picks (the one the benchmark times)
+    # and in the direct-to-LDS configurations
+    Vd, Gd = dev(torch_mod, V), dev(torch_mod, G)
+    best, _ = negf.sigma2b_tune(ctx, Vd, Gd, 2)
+    for cfg in sorted({best, 11, 12}):
+        negf.sigma2b_set_config(ctx, s.n_b, "f64", cfg)
+        got64 = host(negf.sigma2b(ctx, Vd, Gd, 2))
+        errs = {q: relerr(got64[q], r) for q, r in refs.items()}
+        print(f"sigma2b f64 at bench size, configuration {cfg}: max sampled error {max(errs.values()):.2e}")
+        assert all(e < TOL64 for e in errs.values()), (cfg, errs)
+    negf.sigma2b_set_config(ctx, s.n_b, "f64", best)
     # the low-precision modes in the tile configuration their tuner picks. This
     # input decays as e^(-tau) over beta = 50, so the slices near tau = beta are
     # ~1e-45 (slice 1024) and not representable in float32 storage: those are
