@@ -24,6 +24,7 @@
 // first-order recurrences over tau, arranged so that every exponential factor
 // is <= 1 (forward decay or a prefix sum with e^(xi tau) for xi < 0, and the
 // mirror images backwards). G0 itself is added in the same pass.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -410,14 +411,16 @@ int conv_strip_launch(int n, int n_tau, int kind, int block, const double* tau, 
 }
 
 // ------------------------------------------------------------ eigenbasis recurrences
-// Ea[q][k] = e^(-a tau_q), Eb[q][k] = e^(-a (beta - tau_q)), dec[q][k] = e^(-a (tau_(q+1) - tau_q)),
-// a = |eps_k - mu|; cpre[k] = 1 / (1 + e^(-a beta)).
+// Ea[k][q] = e^(-a tau_q), Eb[k][q] = e^(-a (beta - tau_q)), dec[k][q] = e^(-a (tau_(q+1) - tau_q)),
+// a = |eps_k - mu|; cpre[k] = 1 / (1 + e^(-a beta)). The tables are k-major: the
+// recurrences of one workgroup share one or two values of k and walk q, so
+// their table reads are contiguous runs instead of one value per cache line.
 __global__ void k_scan_tables(int n, int n_tau, const double* __restrict__ tau, double beta,
                               const double* __restrict__ eps, double mu, double* Ea, double* Eb, double* dec,
                               double* cpre) {
     const long tot = (long)n * n_tau;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-        const int q = (int)(e / n), k = (int)(e % n);
+        const int k = (int)(e / n_tau), q = (int)(e % n_tau);
         const double a = fabs(eps[k] - mu);
         Ea[e] = exp(-a * tau[q]);
         Eb[e] = exp(-a * (beta - tau[q]));
@@ -449,6 +452,7 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
     const bool ok = e < nn;
     const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
     const bool pos = ok && eps[k] - mu >= 0.0;
+    const long tk = (long)k * n_tau;                 // row k of the k-major tables
     const double c = ok ? cpre[k] : 0.0;
     const int M = n_tau - 1, P = n_tau;
     const int p0 = (int)((long)ch * P / NCH), p1 = (int)((long)(ch + 1) * P / NCH);
@@ -468,12 +472,12 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
                 const double b = (double)In[(long)p * nn + e];
                 if (pos) {
                     if (p < M) {
-                        const double dp = dec[(long)p * n + k];
+                        const double dp = dec[tk + p];
                         acc = dp * (acc + w[p] * b);
                         d *= dp;
                     }
                 } else {
-                    acc += w[p] * Ea[(long)p * n + k] * b;
+                    acc += w[p] * Ea[tk + p] * b;
                 }
             }
         }
@@ -486,10 +490,10 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
                 const double b = (double)In[(long)p * nn + e];
                 if (pos) {
                     Out[(long)p * nn + e] = (T)(c * (acc + hL[p] * b));
-                    if (p < M) acc = dec[(long)p * n + k] * (acc + w[p] * b);
+                    if (p < M) acc = dec[tk + p] * (acc + w[p] * b);
                 } else {
-                    const double ea = Ea[(long)p * n + k];
-                    Out[(long)p * nn + e] = (T)(c * Eb[(long)p * n + k] * (acc + hL[p] * ea * b));
+                    const double ea = Ea[tk + p];
+                    Out[(long)p * nn + e] = (T)(c * Eb[tk + p] * (acc + hL[p] * ea * b));
                     acc += w[p] * ea * b;
                 }
             }
@@ -503,9 +507,9 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
             for (int p = p1 - 1; p >= p0; --p) {
                 const double b = (double)In[(long)p * nn + e];
                 if (pos) {
-                    acc += w[p] * Eb[(long)p * n + k] * b;
+                    acc += w[p] * Eb[tk + p] * b;
                 } else if (p > 0) {
-                    const double dp = dec[(long)(p - 1) * n + k];
+                    const double dp = dec[tk + p - 1];
                     acc = dp * (acc + w[p] * b);
                     d *= dp;
                 }
@@ -521,14 +525,14 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
                 const double b = (double)In[(long)p * nn + e];
                 const double L = (double)Out[(long)p * nn + e];
                 if (pos) {
-                    const double eb = Eb[(long)p * n + k], ea = Ea[(long)p * n + k];
+                    const double eb = Eb[tk + p], ea = Ea[tk + p];
                     const double R = c * ea * (acc + hR[p] * eb * b);
                     acc += w[p] * eb * b;
                     Out[(long)p * nn + e] = (T)(-L + R - c * ea * cjk);
                 } else {
                     const double R = c * (acc + hR[p] * b);
-                    if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b);
-                    Out[(long)p * nn + e] = (T)(-L + R - c * Eb[(long)p * n + k] * cjk);
+                    if (p > 0) acc = dec[tk + p - 1] * (acc + w[p] * b);
+                    Out[(long)p * nn + e] = (T)(-L + R - c * Eb[tk + p] * cjk);
                 }
             }
         }
@@ -557,6 +561,7 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
     const bool ok = e < nn;
     const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
     const bool pos = ok && eps[k] - mu >= 0.0;
+    const long tk = (long)k * n_tau;                 // row k of the k-major tables
     const double c = ok ? cpre[k] : 0.0;
     const int M = n_tau - 1, P = n_tau;
     const int p0 = (int)((long)ch * P / NCH), p1 = (int)((long)(ch + 1) * P / NCH);
@@ -573,12 +578,12 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
                 if (p < p1) {
                     if (pos) {
                         if (p < M) {
-                            const double dp = dec[(long)p * n + k];
+                            const double dp = dec[tk + p];
                             af = dp * (af + w[p] * b[t]);
                             df *= dp;
                         }
                     } else {
-                        af += w[p] * Ea[(long)p * n + k] * b[t];
+                        af += w[p] * Ea[tk + p] * b[t];
                     }
                 }
             }
@@ -587,9 +592,9 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
                 const int p = p0 + t;
                 if (p < p1) {
                     if (pos) {
-                        ab += w[p] * Eb[(long)p * n + k] * b[t];
+                        ab += w[p] * Eb[tk + p] * b[t];
                     } else if (p > 0) {
-                        const double dp = dec[(long)(p - 1) * n + k];
+                        const double dp = dec[tk + p - 1];
                         ab = dp * (ab + w[p] * b[t]);
                         db *= dp;
                     }
@@ -613,10 +618,10 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
             if (p < p1) {
                 if (pos) {
                     L[t] = c * (acc + hL[p] * b[t]);
-                    if (p < M) acc = dec[(long)p * n + k] * (acc + w[p] * b[t]);
+                    if (p < M) acc = dec[tk + p] * (acc + w[p] * b[t]);
                 } else {
-                    const double ea = Ea[(long)p * n + k];
-                    L[t] = c * Eb[(long)p * n + k] * (acc + hL[p] * ea * b[t]);
+                    const double ea = Ea[tk + p];
+                    L[t] = c * Eb[tk + p] * (acc + hL[p] * ea * b[t]);
                     acc += w[p] * ea * b[t];
                 }
             }
@@ -632,14 +637,14 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
             const int p = p0 + t;
             if (p < p1) {
                 if (pos) {
-                    const double eb = Eb[(long)p * n + k], ea = Ea[(long)p * n + k];
+                    const double eb = Eb[tk + p], ea = Ea[tk + p];
                     const double R = c * ea * (acc + hR[p] * eb * b[t]);
                     acc += w[p] * eb * b[t];
                     Out[(long)p * nn + e] = (T)(-L[t] + R - c * ea * cjk);
                 } else {
                     const double R = c * (acc + hR[p] * b[t]);
-                    if (p > 0) acc = dec[(long)(p - 1) * n + k] * (acc + w[p] * b[t]);
-                    Out[(long)p * nn + e] = (T)(-L[t] + R - c * Eb[(long)p * n + k] * cjk);
+                    if (p > 0) acc = dec[tk + p - 1] * (acc + w[p] * b[t]);
+                    Out[(long)p * nn + e] = (T)(-L[t] + R - c * Eb[tk + p] * cjk);
                 }
             }
         }
@@ -710,25 +715,48 @@ __global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T
     if (threadIdx.x == 0) part[q] = tot;
 }
 
+// Static part per row i of rho = -G(beta^-): rowpart[i] = (sum_j h_ij rho_ji,
+// sum_j [sigma rho_ii V_ij rho_jj - V_ij rho_ij rho_ji], rho_ii), one workgroup
+// per row, compensated sums in a fixed order.
 template <class T>
-__global__ __launch_bounds__(256) void k_energy_final(int n, int n_tau, int sigma, const double* __restrict__ h,
-                                                      const double* __restrict__ V, const T* __restrict__ GM,
-                                                      const double* __restrict__ w, const double* __restrict__ part,
-                                                      double* out) {
+__global__ __launch_bounds__(256) void k_energy_rows(int n, int sigma, const double* __restrict__ h,
+                                                     const double* __restrict__ V, const T* __restrict__ GM,
+                                                     double* __restrict__ rowpart) {
+    __shared__ double red[2 * (256 / 64) + 2];
+    const int i = blockIdx.x;
+    const double rii = -(double)GM[(long)i * n + i];
+    CSum c1{0.0, 0.0}, c2{0.0, 0.0};
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const long e = (long)i * n + j;
+        const double rij = -(double)GM[e], rji = -(double)GM[(long)j * n + i];
+        const double rjj = -(double)GM[(long)j * n + j];
+        c1.add(h[e] * rji);
+        c2.add(sigma * rii * V[e] * rjj);
+        c2.add(-(V[e] * rij * rji));
+    }
+    const double e1 = block_csum<256>(c1, red);
+    const double e2 = block_csum<256>(c2, red);
+    if (threadIdx.x == 0) {
+        rowpart[3 * i] = e1;
+        rowpart[3 * i + 1] = e2;
+        rowpart[3 * i + 2] = rii;
+    }
+}
+
+// E = sigma (sum_ij h_ij rho_ji + (1/2) [Hartree - exchange]) - (sigma/2) sum_q w_q part[q];
+// N = sigma Tr rho. One workgroup over the slice and row partials.
+__global__ __launch_bounds__(256) void k_energy_final(int n, int n_tau, int sigma, const double* __restrict__ w,
+                                                      const double* __restrict__ part,
+                                                      const double* __restrict__ rowpart, double* out) {
     __shared__ double red[2 * (256 / 64) + 2];
     CSum cec{0.0, 0.0};
     for (int q = threadIdx.x; q < n_tau; q += 256) cec.add(w[q] * part[q]);
     const double ec = block_csum<256>(cec, red);
-    const long nn = (long)n * n;
     CSum c1{0.0, 0.0}, c2{0.0, 0.0}, ctr{0.0, 0.0};
-    for (long e = threadIdx.x; e < nn; e += 256) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        const double rij = -(double)GM[e], rji = -(double)GM[(long)j * n + i];
-        const double rii = -(double)GM[(long)i * n + i], rjj = -(double)GM[(long)j * n + j];
-        c1.add(h[e] * rji);
-        c2.add(sigma * rii * V[e] * rjj);
-        c2.add(-(V[e] * rij * rji));
-        if (i == j) ctr.add(rii);
+    for (int i = threadIdx.x; i < n; i += 256) {
+        c1.add(rowpart[3 * i]);
+        c2.add(rowpart[3 * i + 1]);
+        ctr.add(rowpart[3 * i + 2]);
     }
     const double e1 = block_csum<256>(c1, red);
     const double e2 = block_csum<256>(c2, red);
@@ -960,8 +988,14 @@ int energy_launch(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, co
     NEGF_TRY(scratch_t(ctx, "en_part", n_tau, &part));
     hipLaunchKernelGGL((k_energy_slices<T>), dim3(n_tau), dim3(256), 0, st, n, n_tau, Sc, G, part);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_energy_final<T>), dim3(1), dim3(256), 0, st, n, n_tau, sigma, h, V,
-                       G + (long)(n_tau - 1) * n * n, (const double*)dw, part, out);
+    double* rowpart;
+    // sized for n up to 1024 at once, so that systems of a batch share one buffer
+    NEGF_TRY(scratch_t(ctx, "en_rowpart", (size_t)3 * std::max(n, 1024), &rowpart));
+    hipLaunchKernelGGL((k_energy_rows<T>), dim3(n), dim3(256), 0, st, n, sigma, h, V, G + (long)(n_tau - 1) * n * n,
+                       rowpart);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, n, n_tau, sigma, (const double*)dw, part,
+                       (const double*)rowpart, out);
     LAUNCH_CHECK();
     return NEGF_OK;
 }

@@ -6,6 +6,8 @@
 // quadrant (2 x 2 MFMA tiles). Panels are staged in LDS k-major so that each
 // lane's operand fetch for one MFMA is a row of 16 consecutive elements, in two
 // buffers (the next panel is loaded while the current one is multiplied).
+#include <type_traits>
+
 #include "common.h"
 #include "mfma.h"
 
@@ -91,25 +93,40 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
             for (int e = 0; e < 4; ++e) Bs[buf][(tid & 3) * 4 + e][tid >> 2] = rb[e];
         }
     };
+    // 16 x 16 blocks of this wave's quadrant that hold some row < M and some
+    // column < N (wave-uniform): blocks wholly in the padding of the last tile
+    // row or column are not multiplied
+    const int wm = __builtin_amdgcn_readfirstlane(m0 + wr * 32), wn = __builtin_amdgcn_readfirstlane(n0 + wc * 32);
+    const int nmi = wm >= M ? 0 : (wm + 16 >= M ? 1 : 2), nni = wn >= N ? 0 : (wn + 16 >= N ? 1 : 2);
+    auto panel = [&](int buf, auto mi_t, auto ni_t) {
+        constexpr int MI = decltype(mi_t)::value, NI = decltype(ni_t)::value;
+#pragma unroll
+        for (int ks = 0; ks < GB_K / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            AFrag<T> a[MI];
+            T bf[NI];
+#pragma unroll
+            for (int i = 0; i < MI; ++i) a[i].load(lane, [&](int m) { return As[buf][kk][wr * 32 + 16 * i + m]; });
+#pragma unroll
+            for (int j = 0; j < NI; ++j) bf[j] = Bs[buf][kk][wc * 32 + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int j = 0; j < NI; ++j) acc[i][j] = a[i].mma(bf[j], acc[i][j]);
+        }
+    };
+    typedef std::integral_constant<int, 1> C1;
+    typedef std::integral_constant<int, 2> C2;
     load(0);
     store(0);
     __syncthreads();
     for (int k0 = 0, buf = 0; k0 < K; k0 += GB_K, buf ^= 1) {
         const bool more = k0 + GB_K < K;
         if (more) load(k0 + GB_K);
-#pragma unroll
-        for (int ks = 0; ks < GB_K / 4; ++ks) {
-            const int kk = ks * 4 + (lane >> 4);
-            AFrag<T> a0, a1;
-            a0.load(lane, [&](int m) { return As[buf][kk][wr * 32 + m]; });
-            a1.load(lane, [&](int m) { return As[buf][kk][wr * 32 + 16 + m]; });
-            T b0 = Bs[buf][kk][wc * 32 + (lane & 15)];
-            T b1 = Bs[buf][kk][wc * 32 + 16 + (lane & 15)];
-            acc[0][0] = a0.mma(b0, acc[0][0]);
-            acc[0][1] = a0.mma(b1, acc[0][1]);
-            acc[1][0] = a1.mma(b0, acc[1][0]);
-            acc[1][1] = a1.mma(b1, acc[1][1]);
-        }
+        if (nmi == 2 && nni == 2) panel(buf, C2(), C2());
+        else if (nmi == 2 && nni == 1) panel(buf, C2(), C1());
+        else if (nmi == 1 && nni == 2) panel(buf, C1(), C2());
+        else if (nmi == 1 && nni == 1) panel(buf, C1(), C1());
         // the other buffer was last read before the previous barrier
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -181,35 +198,50 @@ __global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, 
             Bsi[buf][tid >> 4][(tid & 15) * 4 + e] = rbi[e];
         }
     };
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int k0 = 0, buf = 0; k0 < n; k0 += GB_K, buf ^= 1) {
-        const bool more = k0 + GB_K < n;
-        if (more) load(k0 + GB_K);
+    // as in k_gemm: 16 x 16 blocks wholly in the padding are not multiplied
+    const int wm = __builtin_amdgcn_readfirstlane(m0 + wr * 32), wn = __builtin_amdgcn_readfirstlane(n0 + wc * 32);
+    const int nmi = wm >= n ? 0 : (wm + 16 >= n ? 1 : 2), nni = wn >= n ? 0 : (wn + 16 >= n ? 1 : 2);
+    auto panel = [&](int buf, auto mi_t, auto ni_t) {
+        constexpr int MI = decltype(mi_t)::value, NI = decltype(ni_t)::value;
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            AFrag<T> ar[2], ai[2], nai[2];
-            T br[2], bi[2];
+            AFrag<T> ar[MI], ai[MI], nai[MI];
+            T br[NI], bi[NI];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < MI; ++h) {
                 ar[h].load(lane, [&](int m) { return Asr[buf][kk][wr * 32 + 16 * h + m]; });
                 ai[h].load(lane, [&](int m) { return Asi[buf][kk][wr * 32 + 16 * h + m]; });
                 nai[h] = ai[h].neg();
+            }
+#pragma unroll
+            for (int h = 0; h < NI; ++h) {
                 br[h] = Bsr[buf][kk][wc * 32 + 16 * h + (lane & 15)];
                 bi[h] = Bsi[buf][kk][wc * 32 + 16 * h + (lane & 15)];
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < NI; ++j) {
                     cr[i][j] = ar[i].mma(br[j], cr[i][j]);
                     cr[i][j] = nai[i].mma(bi[j], cr[i][j]);
                     ci[i][j] = ar[i].mma(bi[j], ci[i][j]);
                     ci[i][j] = ai[i].mma(br[j], ci[i][j]);
                 }
         }
+    };
+    typedef std::integral_constant<int, 1> C1;
+    typedef std::integral_constant<int, 2> C2;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int k0 = 0, buf = 0; k0 < n; k0 += GB_K, buf ^= 1) {
+        const bool more = k0 + GB_K < n;
+        if (more) load(k0 + GB_K);
+        if (nmi == 2 && nni == 2) panel(buf, C2(), C2());
+        else if (nmi == 2 && nni == 1) panel(buf, C2(), C1());
+        else if (nmi == 1 && nni == 2) panel(buf, C1(), C2());
+        else if (nmi == 1 && nni == 1) panel(buf, C1(), C1());
         if (more) store(buf ^ 1);
         __syncthreads();
     }
