@@ -109,36 +109,90 @@ constexpr int FFT_UNR = 8;   // loads of a thread in flight at once when filling
 
 __device__ __forceinline__ int bitrev(int x, int L) { return (int)(__brev((unsigned)x) >> (32 - L)); }
 
+// Decimation-in-time stages over CW bit-reversed columns of M = 2^L points in
+// LDS (br, bi), twiddles W_M^j = e^(-2 pi i j / M), j < M/2, in LDS (twr, twi).
+// Stages are taken two at a time as radix-4 butterflies (half the LDS passes
+// and barriers of radix-2); an odd L starts with one radix-2 stage. For the
+// stage pair (s, s+1), h = 2^(s-1), a butterfly takes the points pos, pos+h,
+// pos+2h, pos+3h of a group of 4h (pos < h): stage s pairs (pos, pos+h) and
+// (pos+2h, pos+3h) with W_2h^pos, stage s+1 pairs (pos, pos+2h) with W_4h^pos
+// and (pos+h, pos+3h) with W_4h^(pos+h) = -i W_4h^pos.
 template <class T>
-__device__ void fft_stages(T* br, T* bi, int M, int L, int CW, const T* __restrict__ tw) {
-    for (int s = 1; s <= L; ++s) {
-        const int half = 1 << (s - 1), stride = M >> s;
+__device__ void fft_stages(T* br, T* bi, int M, int L, int CW, const T* __restrict__ twr, const T* __restrict__ twi) {
+    int s = 1;
+    if (L & 1) {
         for (int b = threadIdx.x; b < (M >> 1) * CW; b += blockDim.x) {
             const int w = b / (M >> 1), bb = b % (M >> 1);
-            const int grp = bb >> (s - 1), pos = bb & (half - 1);
-            const int i0 = w * M + grp * 2 * half + pos, i1 = i0 + half;
-            const T twr = tw[2 * pos * stride], twi = tw[2 * pos * stride + 1];
-            const T ar = br[i1], ai = bi[i1];
-            const T tr = ar * twr - ai * twi, ti = ar * twi + ai * twr;
-            const T ur = br[i0], ui = bi[i0];
-            br[i0] = ur + tr;
-            bi[i0] = ui + ti;
-            br[i1] = ur - tr;
-            bi[i1] = ui - ti;
+            const int i0 = w * M + 2 * bb, i1 = i0 + 1;
+            const T ar = br[i1], ai = bi[i1], ur = br[i0], ui = bi[i0];
+            br[i0] = ur + ar;
+            bi[i0] = ui + ai;
+            br[i1] = ur - ar;
+            bi[i1] = ui - ai;
+        }
+        __syncthreads();
+        s = 2;
+    }
+    for (; s < L; s += 2) {
+        const int h = 1 << (s - 1);
+        const int st2 = M >> s, st4 = M >> (s + 1);          // twiddle strides of W_2h and W_4h
+        for (int b = threadIdx.x; b < (M >> 2) * CW; b += blockDim.x) {
+            const int w = b / (M >> 2), bb = b % (M >> 2);
+            const int grp = bb >> (s - 1), pos = bb & (h - 1);
+            const int i0 = w * M + grp * 4 * h + pos;
+            const T a0r = br[i0], a0i = bi[i0], a1r = br[i0 + h], a1i = bi[i0 + h];
+            const T a2r = br[i0 + 2 * h], a2i = bi[i0 + 2 * h], a3r = br[i0 + 3 * h], a3i = bi[i0 + 3 * h];
+            const T w2r = twr[pos * st2], w2i = twi[pos * st2];
+            const T w4r = twr[pos * st4], w4i = twi[pos * st4];
+            // stage s
+            const T t1r = a1r * w2r - a1i * w2i, t1i = a1r * w2i + a1i * w2r;
+            const T t3r = a3r * w2r - a3i * w2i, t3i = a3r * w2i + a3i * w2r;
+            const T b0r = a0r + t1r, b0i = a0i + t1i, b1r = a0r - t1r, b1i = a0i - t1i;
+            const T b2r = a2r + t3r, b2i = a2i + t3i, b3r = a2r - t3r, b3i = a2i - t3i;
+            // stage s + 1: u2 = W_4h^pos b2, u3 = -i W_4h^pos b3
+            const T u2r = b2r * w4r - b2i * w4i, u2i = b2r * w4i + b2i * w4r;
+            const T v3r = b3r * w4r - b3i * w4i, v3i = b3r * w4i + b3i * w4r;
+            const T u3r = v3i, u3i = -v3r;
+            br[i0] = b0r + u2r;
+            bi[i0] = b0i + u2i;
+            br[i0 + 2 * h] = b0r - u2r;
+            bi[i0 + 2 * h] = b0i - u2i;
+            br[i0 + h] = b1r + u3r;
+            bi[i0 + h] = b1i + u3i;
+            br[i0 + 3 * h] = b1r - u3r;
+            bi[i0 + 3 * h] = b1i - u3i;
         }
         __syncthreads();
     }
 }
 
+// Twiddles W_M^j, j < M/2: the global table holds the real parts, then the
+// imaginary parts. With lds set they are copied into LDS after the columns
+// (twr, twi point there on return); otherwise they are read from the table
+// (the largest transforms, whose columns leave no room for them).
+template <class T>
+__device__ __forceinline__ void fft_twiddles(int M, int lds, const T* __restrict__ tw, T* sm, const T*& twr,
+                                             const T*& twi) {
+    if (lds) {
+        for (int j = threadIdx.x; j < M; j += blockDim.x) sm[j] = tw[j];
+        twr = sm;
+    } else {
+        twr = tw;
+    }
+    twi = twr + (M >> 1);
+}
+
 // A_k = sum_{q<M} x^_q e^(-i pi (2k+1) q / M) for k < M/2 and every real column
 // of X [M+1][nc], with x^_0 = (X_0 - X_M)/2. Output planar [M/2][nc].
 template <class T>
-__global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, const T* __restrict__ X,
+__global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, int tw_lds, const T* __restrict__ X,
                                                  const T* __restrict__ twist, const T* __restrict__ tw,
                                                  T* __restrict__ Are, T* __restrict__ Aim) {
     extern __shared__ unsigned char sm_raw[];
     T* br = reinterpret_cast<T*>(sm_raw);
     T* bi = br + CW * M;
+    const T *twr, *twi;
+    fft_twiddles(M, tw_lds, tw, bi + CW * M, twr, twi);
     const long c0 = (long)blockIdx.x * 2 * CW;
     // row q = 0 holds x^_0 = (X_0 - X_M) / 2 (twist factor 1)
     if (threadIdx.x < CW) {
@@ -175,7 +229,7 @@ __global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, 
         }
     }
     __syncthreads();
-    fft_stages(br, bi, M, L, CW, tw);
+    fft_stages(br, bi, M, L, CW, twr, twi);
     for (int idx = threadIdx.x; idx < (M >> 1) * CW; idx += blockDim.x) {
         const int k = idx / CW, w = idx % CW;
         const long c1 = c0 + 2 * w, c2 = c1 + 1;
@@ -195,12 +249,14 @@ __global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, 
 // out_q = (1/M) sum_{k<M} C_k e^(i pi (2k+1) q / M), q < M, for real outputs
 // whose spectra satisfy C_(M-1-k) = conj(C_k); input planar [M/2][nc].
 template <class T>
-__global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, const T* __restrict__ Cre,
+__global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, int tw_lds, const T* __restrict__ Cre,
                                                  const T* __restrict__ Cim, const T* __restrict__ twist,
                                                  const T* __restrict__ tw, T* __restrict__ out) {
     extern __shared__ unsigned char sm_raw[];
     T* br = reinterpret_cast<T*>(sm_raw);
     T* bi = br + CW * M;
+    const T *twr, *twi;
+    fft_twiddles(M, tw_lds, tw, bi + CW * M, twr, twi);
     const long c0 = (long)blockIdx.x * 2 * CW;
     for (int idx = threadIdx.x; idx < (M >> 1) * CW; idx += blockDim.x) {
         const int k = idx / CW, w = idx % CW;
@@ -216,7 +272,7 @@ __global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, 
         bi[r1] = -(b_r - a_i);
     }
     __syncthreads();
-    fft_stages(br, bi, M, L, CW, tw);
+    fft_stages(br, bi, M, L, CW, twr, twi);
     const T sc = T(1) / T(M);
     for (int idx = threadIdx.x; idx < M * CW; idx += blockDim.x) {
         const int q = idx / CW, w = idx % CW;
@@ -803,10 +859,10 @@ int fft_tables(negf_ctx* ctx, int M, hipStream_t st, T** twist, T** tw) {
             a[2 * q] = (T)cosl(th);
             a[2 * q + 1] = (T)sinl(th);
         }
-        for (int k = 0; k < M / 2; ++k) {
+        for (int k = 0; k < M / 2; ++k) {                  // real parts, then imaginary parts
             const long double th = -2.0L * 3.14159265358979323846264338327950288L * k / M;
-            b[2 * k] = (T)cosl(th);
-            b[2 * k + 1] = (T)sinl(th);
+            b[k] = (T)cosl(th);
+            b[M / 2 + k] = (T)sinl(th);
         }
         NEGF_TRY(upload(ctx, (tag + "_twist").c_str(), a.data(), sizeof(T) * a.size(), st, &p1));
         NEGF_TRY(upload(ctx, (tag + "_tw").c_str(), b.data(), sizeof(T) * b.size(), st, &p2));
@@ -831,7 +887,9 @@ int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0,
     int CW = (int)(131072 / ((long)M * 2 * sizeof(T)));
     if (CW < 1) CW = 1;
     if (CW > 32) CW = 32;
-    const size_t smem = (size_t)CW * M * 2 * sizeof(T);
+    // the twiddles (M/2 complex) go into LDS after the columns where they fit
+    const int tw_lds = ((size_t)CW * M * 2 + (size_t)M) * sizeof(T) <= 160 * 1024 ? 1 : 0;
+    const size_t smem = ((size_t)CW * M * 2 + (tw_lds ? (size_t)M : 0)) * sizeof(T);
     const long blocks = ((long)nc + 2 * CW - 1) / (2 * CW);
     const int threads = CW * M >= 4096 ? 1024 : 256;
     static bool attr[2][2] = {{false, false}, {false, false}};
@@ -842,10 +900,10 @@ int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0,
         attr[ti][inverse] = true;
     }
     if (!inverse)
-        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, in0, twist,
+        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, tw_lds, in0, twist,
                            tw, out0, out1);
     else
-        hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, in0, in1,
+        hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, tw_lds, in0, in1,
                            twist, tw, out0);
     LAUNCH_CHECK();
     return NEGF_OK;
