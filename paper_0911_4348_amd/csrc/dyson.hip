@@ -63,7 +63,29 @@ struct CSum {
 };
 
 // Block-wide compensated sum, in a fixed order (waves by butterfly, then the
-// waves' partial sums in wave order by thread 0). red holds 2 (NT/64) + 2 doubles.
+// waves' partial sums in wave order by thread 0), as the unrounded pair (sum,
+// compensation), valid in thread 0. red holds 2 (NT/64) + 2 doubles.
+template <int NT>
+__device__ CSum block_csum_pair(CSum v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double os = __shfl_xor(v.s, off, 64), oc = __shfl_xor(v.c, off, 64);
+        v.merge(os, oc);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) {
+        red[2 * w] = v.s;
+        red[2 * w + 1] = v.c;
+    }
+    __syncthreads();
+    CSum t{red[0], red[1]};
+    if (threadIdx.x == 0)
+        for (int k = 1; k < NT / 64; ++k) t.merge(red[2 * k], red[2 * k + 1]);
+    __syncthreads();
+    return t;
+}
+
+// The same rounded to one double, returned to every thread.
 template <int NT>
 __device__ double block_csum(CSum v, double* red) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -281,16 +303,6 @@ __global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, 
         const T cr = twist[2 * q], ci = twist[2 * q + 1];          // e^(-i pi q/M); multiply by its conjugate
         if (c1 < nc) out[(long)q * nc + c1] = yr * cr + yi * ci;
         if (c2 < nc) out[(long)q * nc + c2] = yi * cr - yr * ci;
-    }
-}
-
-// A'_k = dtau A_k + St (St real, the same for every frequency)
-template <class T>
-__global__ void k_freq_prep(long nn, int nk, T dtau, const T* __restrict__ St, T* __restrict__ Are, T* __restrict__ Aim) {
-    const long tot = nn * nk;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-        Are[e] = dtau * Are[e] + St[e % nn];
-        Aim[e] = dtau * Aim[e];
     }
 }
 
@@ -738,42 +750,64 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, T* G) {
 }
 
 // ------------------------------------------------------------ energy
-// part[q] = Tr[Sc(beta - tau_q) G(tau_q)] = sum_ij S_ij G_ji, float64 products,
-// compensated sum. G is read through LDS one 32 x 32 block at a time, so that
-// both S (block (I, J)) and G (block (J, I)) are read along their rows.
+// part[q][I] = sum over rows i of strip I (32 rows) of sum_j S_ij G_ji with
+// S = Sc(beta - tau_q), G = G(tau_q): float64 products, compensated sums kept
+// as unrounded (sum, compensation) pairs. One
+// workgroup per (q, I); G is read through LDS one 32 x 32 block at a time, so
+// that both S (block (I, J)) and G (block (J, I)) are read along their rows,
+// and a thread's loads for EN_MAXJ blocks of the strip are issued before the
+// first of them is summed. Tr[Sc(beta - tau_q) G(tau_q)] = sum_I part[q][I].
+constexpr int EN_MAXJ = 4;                             // blocks of a strip whose loads are in flight together
 template <class T>
 __global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T* __restrict__ Sc,
                                                        const T* __restrict__ G, double* part) {
     __shared__ double red[2 * (256 / 64) + 2];
     __shared__ double gt[32][33];
-    const int q = blockIdx.x;
+    const int q = blockIdx.x, I = 32 * blockIdx.y, nI = gridDim.y;
     const long nn = (long)n * n;
     const T* S = Sc + (long)(n_tau - 1 - q) * nn;
     const T* g = G + (long)q * nn;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8 threads
+    const int nJ = (n + 31) >> 5;
     CSum s{0.0, 0.0};
-    for (int I = 0; I < n; I += 32)
-        for (int J = 0; J < n; J += 32) {
-            __syncthreads();
-            // gt[c][r] = G[J + r][I + c]: row r of block (J, I), stored transposed
-            for (int r = ty; r < 32; r += 8) {
-                const int gr = J + r, gc = I + tx;
-                gt[tx][r] = (gr < n && gc < n) ? (double)g[(long)gr * n + gc] : 0.0;
+    for (int J0 = 0; J0 < nJ; J0 += EN_MAXJ) {
+        double gv[EN_MAXJ][4], sv[EN_MAXJ][4];
+#pragma unroll
+        for (int jj = 0; jj < EN_MAXJ; ++jj)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int J = 32 * (J0 + jj), r = ty + 8 * u;
+                const bool inb = J0 + jj < nJ;
+                // gv: G[J + r][I + tx] (row r of block (J, I)); sv: S[I + r][J + tx]
+                gv[jj][u] = (inb && J + r < n && I + tx < n) ? (double)g[(long)(J + r) * n + I + tx] : 0.0;
+                sv[jj][u] = (inb && I + r < n && J + tx < n) ? (double)S[(long)(I + r) * n + J + tx] : 0.0;
             }
-            __syncthreads();
-            // S[I + r][J + c] * G[J + c][I + r], G from gt[r][c]
-            for (int r = ty; r < 32; r += 8) {
-                const int i = I + r, j = J + tx;
-                if (i < n && j < n) s.add((double)S[(long)i * n + j] * gt[r][tx]);
+#pragma unroll
+        for (int jj = 0; jj < EN_MAXJ; ++jj) {
+            if (J0 + jj < nJ) {
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < 4; ++u) gt[tx][ty + 8 * u] = gv[jj][u];      // gt[c][r] = G[J + r][I + c]
+                __syncthreads();
+                // S[I + r][J + c] * G[J + c][I + r], G from gt[r][c]
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = ty + 8 * u;
+                    if (I + r < n && 32 * (J0 + jj) + tx < n) s.add(sv[jj][u] * gt[r][tx]);
+                }
             }
         }
-    const double tot = block_csum<256>(s, red);
-    if (threadIdx.x == 0) part[q] = tot;
+    }
+    const CSum tot = block_csum_pair<256>(s, red);
+    if (threadIdx.x == 0) {
+        part[2 * ((long)q * nI + blockIdx.y)] = tot.s;
+        part[2 * ((long)q * nI + blockIdx.y) + 1] = tot.c;
+    }
 }
 
 // Static part per row i of rho = -G(beta^-): rowpart[i] = (sum_j h_ij rho_ji,
 // sum_j [sigma rho_ii V_ij rho_jj - V_ij rho_ij rho_ji], rho_ii), one workgroup
-// per row, compensated sums in a fixed order.
+// per row, compensated sums in a fixed order kept as (sum, compensation) pairs.
 template <class T>
 __global__ __launch_bounds__(256) void k_energy_rows(int n, int sigma, const double* __restrict__ h,
                                                      const double* __restrict__ V, const T* __restrict__ GM,
@@ -790,12 +824,14 @@ __global__ __launch_bounds__(256) void k_energy_rows(int n, int sigma, const dou
         c2.add(sigma * rii * V[e] * rjj);
         c2.add(-(V[e] * rij * rji));
     }
-    const double e1 = block_csum<256>(c1, red);
-    const double e2 = block_csum<256>(c2, red);
+    const CSum e1 = block_csum_pair<256>(c1, red);
+    const CSum e2 = block_csum_pair<256>(c2, red);
     if (threadIdx.x == 0) {
-        rowpart[3 * i] = e1;
-        rowpart[3 * i + 1] = e2;
-        rowpart[3 * i + 2] = rii;
+        rowpart[5 * i] = e1.s;
+        rowpart[5 * i + 1] = e1.c;
+        rowpart[5 * i + 2] = e2.s;
+        rowpart[5 * i + 3] = e2.c;
+        rowpart[5 * i + 4] = rii;
     }
 }
 
@@ -805,14 +841,19 @@ __global__ __launch_bounds__(256) void k_energy_final(int n, int n_tau, int sigm
                                                       const double* __restrict__ part,
                                                       const double* __restrict__ rowpart, double* out) {
     __shared__ double red[2 * (256 / 64) + 2];
+    const int nI = (n + 31) >> 5;
     CSum cec{0.0, 0.0};
-    for (int q = threadIdx.x; q < n_tau; q += 256) cec.add(w[q] * part[q]);
+    for (int q = threadIdx.x; q < n_tau; q += 256) {
+        CSum tq{0.0, 0.0};                                 // Tr[Sc(beta - tau_q) G(tau_q)], strips in order
+        for (int I = 0; I < nI; ++I) tq.merge(part[2 * ((long)q * nI + I)], part[2 * ((long)q * nI + I) + 1]);
+        cec.add(w[q] * tq.value());
+    }
     const double ec = block_csum<256>(cec, red);
     CSum c1{0.0, 0.0}, c2{0.0, 0.0}, ctr{0.0, 0.0};
     for (int i = threadIdx.x; i < n; i += 256) {
-        c1.add(rowpart[3 * i]);
-        c2.add(rowpart[3 * i + 1]);
-        ctr.add(rowpart[3 * i + 2]);
+        c1.merge(rowpart[5 * i], rowpart[5 * i + 1]);
+        c2.merge(rowpart[5 * i + 2], rowpart[5 * i + 3]);
+        ctr.add(rowpart[5 * i + 4]);
     }
     const double e1 = block_csum<256>(c1, red);
     const double e2 = block_csum<256>(c2, red);
@@ -961,9 +1002,8 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
         NEGF_TRY(fft_tables<T>(ctx, M, st, &twist, &tw));
         NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st));
         NEGF_TRY(fft_launch<T>(false, (int)nn, M, G_in, nullptr, Bre, Bim, twist, tw, st));
-        hipLaunchKernelGGL((k_freq_prep<T>), dim3(grid_for(nn * nk)), dim3(256), 0, st, nn, nk, (T)dtau, St, Are, Aim);
-        LAUNCH_CHECK();
-        NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk));
+        // left factor dtau A_k + St (St real, the same for every frequency), formed as the product stages it
+        NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk, (T)dtau, St));
         NEGF_TRY(fft_launch<T>(true, (int)nn, M, Cre, Cim, I1, nullptr, twist, tw, st));
         // end points p = 0 and p = M
         T *Lm, *Rm, *Em, *SR;
@@ -1043,12 +1083,14 @@ int energy_launch(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, co
     void* dw = nullptr;
     NEGF_TRY(upload_cached(ctx, "en_w", w.data(), sizeof(double) * n_tau, st, &dw));
     double* part;
-    NEGF_TRY(scratch_t(ctx, "en_part", n_tau, &part));
-    hipLaunchKernelGGL((k_energy_slices<T>), dim3(n_tau), dim3(256), 0, st, n, n_tau, Sc, G, part);
+    const int nI = (n + 31) / 32;
+    // sized for n up to 1024 at once, so that systems of a batch share one buffer
+    NEGF_TRY(scratch_t(ctx, "en_part", (size_t)2 * n_tau * std::max(nI, 32), &part));
+    hipLaunchKernelGGL((k_energy_slices<T>), dim3(n_tau, nI), dim3(256), 0, st, n, n_tau, Sc, G, part);
     LAUNCH_CHECK();
     double* rowpart;
     // sized for n up to 1024 at once, so that systems of a batch share one buffer
-    NEGF_TRY(scratch_t(ctx, "en_rowpart", (size_t)3 * std::max(n, 1024), &rowpart));
+    NEGF_TRY(scratch_t(ctx, "en_rowpart", (size_t)5 * std::max(n, 1024), &rowpart));
     hipLaunchKernelGGL((k_energy_rows<T>), dim3(n), dim3(256), 0, st, n, sigma, h, V, G + (long)(n_tau - 1) * n * n,
                        rowpart);
     LAUNCH_CHECK();
