@@ -59,12 +59,10 @@ int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha,
          T beta, const T* Cin, long ldci, long sCi, T* C, long ldc, long sC,
          int batch, const T* colscale = nullptr, long sS = 0);
 // Batched complex product of n x n matrices in planar form: Cr + i Ci =
-// (a (Ar + i Ai) + Ad)(Br + i Bi), matrix b of each array at offset b * stride,
-// with a real scale a of the left factor and a real n x n matrix Ad (nullable)
-// added to every left factor as it is read.
+// (Ar + i Ai)(Br + i Bi), matrix b of each array at offset b * stride.
 template <class T>
 int cgemm(hipStream_t st, int n, const T* Ar, const T* Ai, const T* Br, const T* Bi, T* Cr, T* Ci, long stride,
-          int batch, T a = T(1), const T* Ad = nullptr);
+          int batch);
 
 // ---------------------------------------------------------------- HF pieces
 // Work list of the persistent Sigma-2B kernel for a batch of systems.

@@ -205,11 +205,13 @@ __device__ __forceinline__ void fft_twiddles(int M, int lds, const T* __restrict
 }
 
 // A_k = sum_{q<M} x^_q e^(-i pi (2k+1) q / M) for k < M/2 and every real column
-// of X [M+1][nc], with x^_0 = (X_0 - X_M)/2. Output planar [M/2][nc].
+// of X [M+1][nc], with x^_0 = (X_0 - X_M)/2. Output planar [M/2][nc], written
+// as s A_k + D (s real; D real [nc], nullable, added to every real part).
 template <class T>
 __global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, int tw_lds, const T* __restrict__ X,
-                                                 const T* __restrict__ twist, const T* __restrict__ tw,
-                                                 T* __restrict__ Are, T* __restrict__ Aim) {
+                                                 const T* __restrict__ twist, const T* __restrict__ tw, T osc,
+                                                 const T* __restrict__ oadd, T* __restrict__ Are,
+                                                 T* __restrict__ Aim) {
     extern __shared__ unsigned char sm_raw[];
     T* br = reinterpret_cast<T*>(sm_raw);
     T* bi = br + CW * M;
@@ -258,12 +260,12 @@ __global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, 
         const T zr = br[w * M + k], zi = bi[w * M + k];
         const T yr = br[w * M + M - 1 - k], yi = bi[w * M + M - 1 - k];
         if (c1 < nc) {
-            Are[(long)k * nc + c1] = T(0.5) * (zr + yr);
-            Aim[(long)k * nc + c1] = T(0.5) * (zi - yi);
+            Are[(long)k * nc + c1] = osc * (T(0.5) * (zr + yr)) + (oadd ? oadd[c1] : T(0));
+            Aim[(long)k * nc + c1] = osc * (T(0.5) * (zi - yi));
         }
         if (c2 < nc) {
-            Are[(long)k * nc + c2] = T(0.5) * (zi + yi);
-            Aim[(long)k * nc + c2] = T(-0.5) * (zr - yr);
+            Are[(long)k * nc + c2] = osc * (T(0.5) * (zi + yi)) + (oadd ? oadd[c2] : T(0));
+            Aim[(long)k * nc + c2] = osc * (T(-0.5) * (zr - yr));
         }
     }
 }
@@ -919,7 +921,7 @@ int fft_tables(negf_ctx* ctx, int M, hipStream_t st, T** twist, T** tw) {
 
 template <class T>
 int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0, T* out1, const T* twist,
-               const T* tw, hipStream_t st) {
+               const T* tw, hipStream_t st, T oscale = T(1), const T* oadd = nullptr) {
     int L = 0;
     while ((1 << L) < M) ++L;
     // 128 KB of LDS per workgroup: at M = 1024 that is 16 real columns in float64
@@ -942,7 +944,7 @@ int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0,
     }
     if (!inverse)
         hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, tw_lds, in0, twist,
-                           tw, out0, out1);
+                           tw, oscale, oadd, out0, out1);
     else
         hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, tw_lds, in0, in1,
                            twist, tw, out0);
@@ -1000,10 +1002,10 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
         NEGF_TRY(scratch_t(ctx, "dy_Cre", nn * nk, &Cre));
         NEGF_TRY(scratch_t(ctx, "dy_Cim", nn * nk, &Cim));
         NEGF_TRY(fft_tables<T>(ctx, M, st, &twist, &tw));
-        NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st));
+        // A'_k = dtau A_k + St (St real, the same for every frequency), formed as the transform writes A_k
+        NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st, (T)dtau, St));
         NEGF_TRY(fft_launch<T>(false, (int)nn, M, G_in, nullptr, Bre, Bim, twist, tw, st));
-        // left factor dtau A_k + St (St real, the same for every frequency), formed as the product stages it
-        NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk, (T)dtau, St));
+        NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk));
         NEGF_TRY(fft_launch<T>(true, (int)nn, M, Cre, Cim, I1, nullptr, twist, tw, st));
         // end points p = 0 and p = M
         T *Lm, *Rm, *Em, *SR;

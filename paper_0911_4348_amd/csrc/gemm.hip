@@ -147,9 +147,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
 }
 
 // Batched complex product C = A B of n x n matrices in planar form (real and
-// imaginary parts in separate arrays, matrix b at offset b * stride), the left
-// factor taken as a A + Ad (a real, Ad a real matrix shared by the batch,
-// nullable) while it is staged:
+// imaginary parts in separate arrays, matrix b at offset b * stride):
 //   Cr = Ar Br - Ai Bi,  Ci = Ar Bi + Ai Br,
 // each part accumulated in one chain over k. The tile layout, staging and
 // XCD order are those of k_gemm; every operand tile is read once for both
@@ -158,8 +156,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, cons
 template <class T>
 __global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, const T* __restrict__ Ai,
                                                const T* __restrict__ Br, const T* __restrict__ Bi,
-                                               T* __restrict__ Cr, T* __restrict__ Ci, long stride, T asc,
-                                               const T* __restrict__ Ad) {
+                                               T* __restrict__ Cr, T* __restrict__ Ci, long stride) {
     __shared__ T Asr[2][GB_K][GB_M + GB_PAD], Asi[2][GB_K][GB_M + GB_PAD];
     __shared__ T Bsr[2][GB_K][GB_N + GB_PAD], Bsi[2][GB_K][GB_N + GB_PAD];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -179,8 +176,8 @@ __global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, 
             for (int e = 0; e < 4; ++e) {
                 const int k = kb + e;
                 const bool in = m < n && k < n;
-                rar[e] = in ? asc * Ar[off + (long)m * n + k] + (Ad ? Ad[(long)m * n + k] : T(0)) : T(0);
-                rai[e] = in ? asc * Ai[off + (long)m * n + k] : T(0);
+                rar[e] = in ? Ar[off + (long)m * n + k] : T(0);
+                rai[e] = in ? Ai[off + (long)m * n + k] : T(0);
             }
         }
         {
@@ -264,22 +261,22 @@ __global__ __launch_bounds__(256) void k_cgemm(int n, const T* __restrict__ Ar, 
 
 template <class T>
 int cgemm(hipStream_t st, int n, const T* Ar, const T* Ai, const T* Br, const T* Bi, T* Cr, T* Ci, long stride,
-          int batch, T a, const T* Ad) {
+          int batch) {
     if (n <= 0 || batch <= 0) return NEGF_OK;
     for (int b0 = 0; b0 < batch; b0 += 65535) {
         const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
         const long o = (long)b0 * stride;
         dim3 grid((n + GB_N - 1) / GB_N, (n + GB_M - 1) / GB_M, nb);
         hipLaunchKernelGGL((k_cgemm<T>), grid, dim3(256), 0, st, n, Ar + o, Ai + o, Br + o, Bi + o, Cr + o, Ci + o,
-                           stride, a, Ad);
+                           stride);
         LAUNCH_CHECK();
     }
     return NEGF_OK;
 }
 template int cgemm<double>(hipStream_t, int, const double*, const double*, const double*, const double*, double*,
-                           double*, long, int, double, const double*);
+                           double*, long, int);
 template int cgemm<float>(hipStream_t, int, const float*, const float*, const float*, const float*, float*, float*,
-                          long, int, float, const float*);
+                          long, int);
 
 template <class T>
 int gemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, T alpha, const T* A, long lda,
