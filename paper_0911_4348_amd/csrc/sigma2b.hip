@@ -775,56 +775,64 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
         }
     }
 
-    // direct term D_ij = sum_l T1_il V_lj (V tiles double-buffered through the
-    // stage area), then one store per output element
-    constexpr int DM = (JW + 63) / 64;
-    for (int j0 = 0; j0 < np; j0 += JW) {
-        const int jw = min(JW, np - j0);
-        double d[DM];
+    // The output phase takes its per-lane indices from an opaque copy of the
+    // thread index, so that none computed before the loops has to stay live
+    // (and spill) through them.
+    int tid_o = threadIdx.x;
+    asm volatile("" : "+v"(tid_o));
+    {
+        const int tid = tid_o, lane = tid & 63, w = tid >> 6, i = iblk * IB + w;
+        // direct term D_ij = sum_l T1_il V_lj (V tiles double-buffered through the
+        // stage area), then one store per output element
+        constexpr int DM = (JW + 63) / 64;
+        for (int j0 = 0; j0 < np; j0 += JW) {
+            const int jw = min(JW, np - j0);
+            double d[DM];
 #pragma unroll
-        for (int m = 0; m < DM; ++m) d[m] = 0.0;
-        if (one_chunk) {
+            for (int m = 0; m < DM; ++m) d[m] = 0.0;
+            if (one_chunk) {
 #pragma unroll
-            for (int m = 0; m < DM; ++m)
-                if (lane + 64 * m < jw) d[m] = Ds[w * np + lane + 64 * m];
-        } else {
-            auto issue_v = [&](int l0, int buf) {
-                copy<NT>(stage + buf * L::STAGE_EL, 8 * jw, tid, [&](int c) {
-                    const int hp = jw >> 1, ll = c / hp, jp = c - ll * hp;
-                    return Vp + (long)(l0 + ll) * np + j0 + 2 * jp;
-                });
-            };
-            issue_v(0, 0);
-            int b = 0;
-            for (int l0 = 0; l0 < n; l0 += 16, b ^= 1) {
-                wait_loads();
-                __syncthreads();
-                if (l0 + 16 < n) issue_v(l0 + 16, b ^ 1);
-                const double* Vv = stage + b * L::STAGE_EL;
-                for (int ll = 0; ll < 16; ++ll) {
-                    const double t = T1s[w * np + l0 + ll];      // zero beyond n
+                for (int m = 0; m < DM; ++m)
+                    if (lane + 64 * m < jw) d[m] = Ds[w * np + lane + 64 * m];
+            } else {
+                auto issue_v = [&](int l0, int buf) {
+                    copy<NT>(stage + buf * L::STAGE_EL, 8 * jw, tid, [&](int c) {
+                        const int hp = jw >> 1, ll = c / hp, jp = c - ll * hp;
+                        return Vp + (long)(l0 + ll) * np + j0 + 2 * jp;
+                    });
+                };
+                issue_v(0, 0);
+                int b = 0;
+                for (int l0 = 0; l0 < n; l0 += 16, b ^= 1) {
+                    wait_loads();
+                    __syncthreads();
+                    if (l0 + 16 < n) issue_v(l0 + 16, b ^ 1);
+                    const double* Vv = stage + b * L::STAGE_EL;
+                    for (int ll = 0; ll < 16; ++ll) {
+                        const double t = T1s[w * np + l0 + ll];      // zero beyond n
 #pragma unroll
-                    for (int m = 0; m < DM; ++m)
-                        if (lane + 64 * m < jw) d[m] += t * Vv[ll * jw + lane + 64 * m];
+                        for (int m = 0; m < DM; ++m)
+                            if (lane + 64 * m < jw) d[m] += t * Vv[ll * jw + lane + 64 * m];
+                    }
                 }
             }
-        }
-        if (i < n) {
-            const double* Gu = G + (long)q * nn;
-            const double* Gbu = G + (long)qb * nn;
-            double* Sq = Sc + (long)q * nn;
-            double* Sqb = Sc + (long)qb * nn;
+            if (i < n) {
+                const double* Gu = G + (long)q * nn;
+                const double* Gbu = G + (long)qb * nn;
+                double* Sq = Sc + (long)q * nn;
+                double* Sqb = Sc + (long)qb * nn;
 #pragma unroll
-            for (int m = 0; m < DM; ++m) {
-                const int j = j0 + lane + 64 * m;
-                if (lane + 64 * m < jw && j < n) {
-                    const long ij = (long)i * n + j;
-                    Sq[ij] = sigma * Gu[ij] * d[m] - Xs[w * np + j];
-                    if (!middle) Sqb[ij] = sigma * Gbu[ij] * d[m] - XPs[w * np + j];
+                for (int m = 0; m < DM; ++m) {
+                    const int j = j0 + lane + 64 * m;
+                    if (lane + 64 * m < jw && j < n) {
+                        const long ij = (long)i * n + j;
+                        Sq[ij] = sigma * Gu[ij] * d[m] - Xs[w * np + j];
+                        if (!middle) Sqb[ij] = sigma * Gbu[ij] * d[m] - XPs[w * np + j];
+                    }
                 }
             }
+            __syncthreads();                             // before the next chunk reuses the stage area
         }
-        __syncthreads();                             // before the next chunk reuses the stage area
     }
 }
 
