@@ -36,9 +36,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "7d2c805646dd4f94"
-TRAFFIC_F64_NB199 = {0: 656742590, 1: 656969179, 2: 656790252, 3: 657682137, 4: 657391888, 5: 1165370103,
-                     8: 660867600, 9: 663135249, 10: 662119021}
+TRAFFIC_SRC_SHA256 = "8538ee388b79f00e"
+TRAFFIC_F64_NB199 = {0: 656760591, 1: 657087079, 2: 656924007, 3: 657608886, 4: 657639620, 5: 1954087478,
+                     8: 663992569, 9: 665152955, 10: 663922478, 11: 827520557, 12: 1526072157}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):
@@ -409,7 +409,8 @@ def main():
                                "1025 tau points, beta=50, seeded symmetric G ~ N(0,0.1^2) e^(-tau); "
                                "step = negf_sigma2b + negf_dyson_step (FFT route, float64 energy)",
                    "n_b": n, "n_tau": n_tau, "beta": s.beta},
-        "roofline": {"kernel": "k_sigma2b", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+        "roofline": {"kernel": ("k_sigma2b_dma" if best in (11, 12) else
+                                ("k_sigma2b_valu" if best in (8, 9, 10) else "k_sigma2b")), "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": measured_traffic(args.dtype, n, n_tau, best),
                      "algorithmic_bytes": int(sigma2b_bytes(n, n_tau, elem))},

@@ -817,8 +817,9 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
                 }
             }
             if (i < n) {
-                const double* Gu = G + (long)q * nn;
-                const double* Gbu = G + (long)qb * nn;
+                // G_ij of slice q from the padded copy (its rows were streamed
+                // through the L2 by the panels just before), of slice q' from
+                // the row already in LDS
                 double* Sq = Sc + (long)q * nn;
                 double* Sqb = Sc + (long)qb * nn;
 #pragma unroll
@@ -826,8 +827,8 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
                     const int j = j0 + lane + 64 * m;
                     if (lane + 64 * m < jw && j < n) {
                         const long ij = (long)i * n + j;
-                        Sq[ij] = sigma * Gu[ij] * d[m] - Xs[w * np + j];
-                        if (!middle) Sqb[ij] = sigma * Gbu[ij] * d[m] - XPs[w * np + j];
+                        Sq[ij] = sigma * Gq[(long)i * np + j] * d[m] - Xs[w * np + j];
+                        if (!middle) Sqb[ij] = sigma * Gbi[w * npj + j] * d[m] - XPs[w * np + j];
                     }
                 }
             }
