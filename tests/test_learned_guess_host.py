@@ -35,16 +35,16 @@ def _log(energies, ms=10.0):
     return rows
 
 
-def test_time_to_stopping_rule_and_reference():
+def test_time_to_reference_accuracy():
     E = [-1.0, -1.2, -1.25, -1.2501, -1.250101, -1.2501011]
     rows = _log(E, ms=10.0)
     wall = 1.0                                   # 0.94 s of set-up before the first record
-    k, t, Ek = LG._time_to(rows, wall, 1e-3)     # |dE| < 1e-3 first at step 3
-    assert k == 3 and Ek == E[3] and t == pytest.approx(0.94 + 0.04)
-    k, t, Ek = LG._time_to(rows, wall, 1e-6, E_ref=-1.2501011)   # |E - E_ref| < 1e-6 first at step 4
+    k, t = LG._time_to(rows, wall, 1e-6, -1.2501011)   # |E - E_ref| < 1e-6 first at step 4
     assert k == 4 and t == pytest.approx(0.94 + 0.05)
-    k, t, Ek = LG._time_to(rows, wall, 1e-12, E_ref=0.0)        # never: the whole run
-    assert k == len(E) - 1 and t == wall and Ek == E[-1]
+    k, t = LG._time_to(rows, wall, 1e-3, -1.2501011)   # |E_2 - E_ref| = 1.0e-4 < 1e-3 first
+    assert k == 2 and t == pytest.approx(0.94 + 0.03)
+    k, t = LG._time_to(rows, wall, 1e-12, 0.0)          # never: the whole run
+    assert k == len(E) - 1 and t == wall
 
 
 def test_weights_round_trip_without_pickle(tmp_path):
