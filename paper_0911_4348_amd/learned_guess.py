@@ -77,12 +77,13 @@ def _dev_setup(torch, negf, sysd):
     return x, d(x), d(v), d(tau), (T, v, V)
 
 
-def generate(seeds, tol=1e-5, refine_tol=1e-9, dtype="bf16", chunk=16, log=print, save_path=None):
+def generate(seeds, tol=1e-5, refine_tol=1e-9, dtype="bf16", chunk=16, max_iter=150, log=print, save_path=None):
     """Converged G for each seeded random potential on the n_b = 199 grid, and the
     targets dG at its sample points. Returns float32 [len(seeds), N_SAMPLES].
     The batched SCF runs the low-precision loop to tol and then float64 steps
     until the contraction-aware bound on |E - E_inf| is below refine_tol, so the
-    targets are those of the float64 fixed point."""
+    targets are those of the float64 fixed point. Systems not converged within
+    max_iter steps (the batch waits for its slowest member) are excluded."""
     torch, negf, W = _imports()
     ctx = negf.Context(0)
     seeds = list(seeds)
@@ -93,7 +94,7 @@ def generate(seeds, tol=1e-5, refine_tol=1e-9, dtype="bf16", chunk=16, log=print
         sub = seeds[c0:c0 + chunk]
         systems = [W.random_potential_system(s) for s in sub]
         res = negf.scf_batched(ctx, systems, tol=tol, dtype=dtype, refine_tol=refine_tol, conv=negf.CONV_FFT,
-                               max_iter=400, allow_noconv=True, tune=True, stop="contraction")
+                               max_iter=max_iter, allow_noconv=True, tune=True, stop="contraction")
         # G0 of each system: batched HF (same grid) and the HF Green's function
         mats = [negf.fedvr_build_system(s) for s in systems]
         d = lambda a: torch.from_numpy(np.ascontiguousarray(np.stack(a))).cuda()

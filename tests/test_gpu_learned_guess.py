@@ -1,7 +1,10 @@
-"""What the trained network gains: on held-out random potentials (the learned-
-guess workload: n_b = 199, 1025 tau points, beta = 50) the SCF started from
-G0 + the network's correction reaches |E - E_ref| < 1e-6 Ha in fewer steps than
-the HF start, and both starts converge to the same energy."""
+"""What the trained network gains: on a contiguous block of held-out random
+potentials (the learned-guess workload: n_b = 199, 1025 tau points, beta = 50)
+the SCF started from G0 + the network's correction stops, by the library's own
+contraction-aware rule at 1e-6 Ha, after fewer steps on average than the HF
+start, and both stop within 2e-6 Ha of the reference energy (the HF-started run
+continued to a 1e-10 bound; the rule estimates the geometric tail from the last
+ratios of energy changes, so a run can end slightly above its tolerance)."""
 import os
 
 import numpy as np
@@ -13,6 +16,8 @@ from paper_0911_4348_amd import learned_guess as LG
 
 pytestmark = pytest.mark.gpu
 
+SEEDS = range(100000, 100016)          # the first 16 held-out potentials
+
 
 @pytest.fixture(scope="module")
 def torch_mod():
@@ -20,13 +25,6 @@ def torch_mod():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch
-
-
-def _steps_to(log, E_ref, tol=1e-6):
-    for k, r in enumerate(log):
-        if abs(r["E"] - E_ref) < tol:
-            return k
-    return len(log)
 
 
 def test_trained_weights_are_shipped():
@@ -41,15 +39,26 @@ def test_learned_start_saves_steps_at_equal_energy(torch_mod):
     ctx = negf.Context(0)
     p, scale, _ = LG.load()
     P = torch.from_numpy(p).cuda()
-    hf_steps, lg_steps = [], []
-    for seed in (100000, 100007, 100016):
-        print(f"learned guess seed {seed}", flush=True)
+    kw = dict(conv=negf.CONV_FFT, want_G=False, max_iter=600, allow_noconv=True, stop="contraction")
+    rows = []
+    print("seed     E_ref            HF start: steps |E-E_ref|   learned: steps |E-E_ref|", flush=True)
+    for seed in SEEDS:
         s = W.random_potential_system(seed)
-        a = negf.scf(ctx, s, tol=1e-8, conv=negf.CONV_FFT, want_G=False, max_iter=400)
-        b = negf.scf(ctx, s, tol=1e-8, conv=negf.CONV_FFT, want_G=False, max_iter=400, guess=P, guess_scale=scale)
-        assert abs(a.E - b.E) < 2e-7, (seed, a.E, b.E)      # same fixed point
-        hf_steps.append(_steps_to(a.log, a.E))
-        lg_steps.append(_steps_to(b.log, a.E))
-        print(f"  steps to 1e-6 Ha: HF start {hf_steps[-1]}, learned start {lg_steps[-1]}")
-    assert sum(lg_steps) < sum(hf_steps)
+        ref = negf.scf(ctx, s, tol=1e-10, **kw)
+        if ref.status != negf.OK:
+            print(f"{seed}  skipped: the HF-started SCF itself ends with status {ref.status}", flush=True)
+            continue
+        a = negf.scf(ctx, s, tol=1e-6, **kw)
+        b = negf.scf(ctx, s, tol=1e-6, guess=P, guess_scale=scale, **kw)
+        ea, eb = abs(a.E - ref.E), abs(b.E - ref.E)
+        rows.append((seed, a.iters, b.iters, ea, eb))
+        print(f"{seed}  {ref.E:.10f}  {a.iters:5d} {ea:9.1e}        {b.iters:5d} {eb:9.1e}", flush=True)
+        assert a.status == negf.OK and b.status == negf.OK, seed
+        assert ea < 2e-6 and eb < 2e-6, (seed, ea, eb)       # equal final energy
     ctx.close()
+    hf = np.array([r[1] for r in rows], float)
+    lg = np.array([r[2] for r in rows], float)
+    print(f"{len(rows)} potentials: mean steps HF start {hf.mean():.2f}, learned start {lg.mean():.2f}; "
+          f"fewer for {int((lg < hf).sum())}, more for {int((lg > hf).sum())}", flush=True)
+    assert len(rows) >= 12
+    assert lg.mean() < hf.mean()
