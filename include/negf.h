@@ -235,10 +235,12 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
  * k-panels; 6, 7 (NEGF_F32 and NEGF_BF16 only) = 4 waves with two values of i
  * each x 112- or 64-column chunks; 8, 9, 10 (NEGF_F64 only) = float64 vector-ALU
  * tiles: 8 waves x 40 x 40 blocks of M^(i), 4 waves with two values of i each x
- * 40 x 40 or 32 x 32 blocks; 11, 12 (NEGF_F64 only) = 8 or 4 values of i x
- * 208-column chunks whose k-panels are staged by direct global-to-LDS loads,
- * double-buffered, from zero-padded copies of G and V kept in context scratch
- * (n_tau * np^2 + np^2 doubles, np = n_b rounded up to 16; n_b <= 240 for 11).
+ * 40 x 40 or 32 x 32 blocks; 11, 12 (NEGF_F64 only) = 208-column chunks whose
+ * k-panels are staged by direct global-to-LDS loads, double-buffered, from
+ * zero-padded copies of G and V kept in context scratch (n_tau * np^2 + np^2
+ * doubles, np = n_b rounded up to 16): 11 with 8 values of i and k-panels of
+ * 16 (one workgroup per compute unit; n_b <= 240), 12 with 4 values of i and
+ * k-panels of 4 (75 KB of LDS at n_b <= 208, two workgroups per compute unit).
  * The float64 matrix-core tiles (0-5, 11, 12) run on the four-block 4x4x4
  * float64 MFMA shape. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);

@@ -545,18 +545,23 @@ __device__ __forceinline__ void s2b_tile(int n, int n_tau, int pair, int iblk, t
 // the padding is exact zeros.
 namespace dma {
 
-constexpr int BK = 16;                       // k-panel
-// A panel [16 l][16 k]: 16-byte piece kp (k = 2 kp, 2 kp + 1) of row l is
-// stored at piece kp ^ (l & 7) of that row, so the fragment reads of four
-// rows 128 bytes apart spread over the banks.
-__device__ __forceinline__ int a_index(int l, int k) { return l * 16 + ((((k >> 1) ^ (l & 7))) << 1) + (k & 1); }
+// A panel [16 l][BK k]. With BK = 16 the 16-byte piece kp (k = 2 kp, 2 kp + 1)
+// of row l is stored at piece kp ^ (l & 7) of that row, so the fragment reads
+// of four rows 128 bytes apart spread over the banks; with BK = 4 the four rows
+// a fragment read touches are 32 bytes apart and the layout is plain.
+template <int BK>
+__device__ __forceinline__ int a_index(int l, int k) {
+    if constexpr (BK == 16) return l * 16 + ((((k >> 1) ^ (l & 7))) << 1) + (k & 1);
+    else return l * BK + k;
+}
 
-template <int IB, int JB>
+template <int IB, int JB, int BK>
 struct Layout {
+    static_assert(BK == 16 || BK == 4, "k-panel of 16 or 4");
     static constexpr int JW = JB * 16;
     static constexpr int B_EL = BK * JW;             // B panel [BK][jw] (row stride jw of the chunk)
-    static constexpr int A_EL = 16 * 16;
-    static constexpr int V_EL = IB * 16;             // V panel [IB][BK]
+    static constexpr int A_EL = 16 * BK;
+    static constexpr int V_EL = IB * BK;             // V panel [IB][BK]
     static constexpr int STAGE_EL = B_EL + A_EL + V_EL;
     static constexpr int VT_EL = 16 * JW + IB * 16;  // V tile of the epilogue [16][jw], then G_il [IB][16]
     // one column chunk: the direct term is accumulated in the l-tile loop,
@@ -592,11 +597,11 @@ __device__ __forceinline__ void copy(double* dst, int count, int tid, F src) {
 
 __device__ __forceinline__ void wait_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <int IB, int JB>
+template <int IB, int JB, int BK>
 __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int iblk, double sigma,
                                      const double* __restrict__ Vp, const double* __restrict__ Gp,
                                      const double* __restrict__ G, double* __restrict__ Sc, double* smem) {
-    typedef Layout<IB, JB> L;
+    typedef Layout<IB, JB, BK> L;
     constexpr int NT = IB * 64;
     constexpr int JW = L::JW;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -631,42 +636,52 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
         const int jw = min(JW, np - j0);
         const int njb = jw >> 4;
         // Element offsets of this lane's 16-byte pieces, the same for every panel
-        // of the chunk: piece base + lane of a [16][jw] block (B panel, V tile)
-        // is row c / (jw/2), columns 2 (c % (jw/2)) + 0, 1; A and V pieces as in
-        // the panel layouts. A piece that does not exist gets -1.
-        constexpr int NPB = (16 * (JW / 2) + NT - 1) / NT;      // B / V-tile pieces per lane
+        // of the chunk: piece c of a [rows][jw] block (B panel: BK rows, V tile:
+        // 16 rows) is row c / (jw/2), columns 2 (c % (jw/2)) + 0, 1; the waves
+        // take 64 consecutive pieces each in turn. A and V pieces as in the
+        // panel layouts.
+        constexpr int NPV = (16 * (JW / 2) + NT - 1) / NT;      // V-tile pieces per lane
+        constexpr int NPB = (BK * (JW / 2) + NT - 1) / NT;      // B-panel pieces per lane
         // (byte offsets; ~0u marks a piece that does not exist)
         constexpr unsigned kNone = ~0u;
-        unsigned offb[NPB];
-        {
-            const int hp = jw >> 1;
+        const int hp = jw >> 1;
+        unsigned offb[NPV];
 #pragma unroll
-            for (int t = 0; t < NPB; ++t) {
-                const int c = w * 64 + t * NT + lane;
-                const int kk = c / hp, jp = c - kk * hp;
-                offb[t] = c < 16 * hp ? 8u * (unsigned)(kk * np + j0 + 2 * jp) : kNone;
-            }
+        for (int t = 0; t < NPV; ++t) {
+            const int c = w * 64 + t * NT + lane;
+            const int kk = c / hp, jp = c - kk * hp;
+            offb[t] = c < 16 * hp ? 8u * (unsigned)(kk * np + j0 + 2 * jp) : kNone;
         }
-        const int ca = tid - (NT - 128);             // A pieces: the last two waves
-        const unsigned offa = ca >= 0 ? 8u * (unsigned)((ca >> 3) * np + 2 * ((ca & 7) ^ ((ca >> 3) & 7))) : kNone;
+        // A pieces (16 rows of BK/2): the last waves; V pieces (IB rows of BK/2):
+        // the wave before them
+        constexpr int NA = 16 * BK / 2, AW = (NA + 63) / 64;
+        const int ca = tid - (NT - 64 * AW);
+        const int ra = ca / (BK / 2), pa = ca % (BK / 2);
+        const unsigned offa =
+            (ca >= 0 && ca < NA) ? 8u * (unsigned)(ra * np + 2 * (BK == 16 ? (pa ^ (ra & 7)) : pa)) : kNone;
         const int cg = tid - 128;                    // G_il pieces of the epilogue: the third wave
-        const int cv = tid - (NT - 192);             // V pieces: the wave before them
-        const unsigned offv =
-            (cv >= 0 && cv < IB * 8) ? 8u * (unsigned)((iblk * IB + (cv >> 3)) * np + 2 * (cv & 7)) : kNone;
-        // all 16 x jw pieces of the [16][jw] block of M (row stride np) that
-        // starts row0 rows down, into dst. The row offset is added to the 32-bit
-        // piece offsets (one slice is far below 4 GiB) and the base stays the
-        // slice pointer, so no 64-bit address is kept per piece across panels.
-        auto copy_rows = [&](double* dst, const double* M, int row0) {
+        const int cv = tid - (NT - 64 * AW - 64);
+        const unsigned offv = (cv >= 0 && cv < IB * BK / 2)
+                                  ? 8u * (unsigned)((iblk * IB + cv / (BK / 2)) * np + 2 * (cv % (BK / 2)))
+                                  : kNone;
+        // all pieces of the [rows][jw] block of M (row stride np) that starts
+        // row0 rows down, into dst. The row offset is added to the 32-bit piece
+        // offsets (one slice is far below 4 GiB) and the base stays the slice
+        // pointer, so no 64-bit address is kept per piece across panels.
+        auto copy_rows = [&](double* dst, const double* M, int row0, auto rows_t) {
+            constexpr int ROWS = decltype(rows_t)::value;
+            constexpr int NP = ROWS == 16 ? NPV : NPB;
             const unsigned ro = 8u * (unsigned)(row0 * np);
 #pragma unroll
-            for (int t = 0; t < NPB; ++t)
-                if (offb[t] != kNone) load16(M, offb[t] + ro, dst + 2 * (w * 64 + t * NT));
+            for (int t = 0; t < NP; ++t) {
+                const bool ok = ROWS == 16 ? offb[t] != kNone : (w * 64 + t * NT + lane < ROWS * hp);
+                if (ok) load16(M, offb[t] + ro, dst + 2 * (w * 64 + t * NT));
+            }
         };
         auto issue = [&](int l0, int pn, int buf) {
             double* sb = stage + buf * L::STAGE_EL;
             const int k0 = pn * BK;
-            copy_rows(sb, Gq, k0);
+            copy_rows(sb, Gq, k0, std::integral_constant<int, BK>());
             if (offa != kNone) load16(Gb, offa + 8u * (unsigned)(l0 * np + k0), sb + L::B_EL + 2 * (ca & ~63));
             if (offv != kNone) load16(Vp, offv + 8u * (unsigned)k0, sb + L::B_EL + L::A_EL + 2 * (cv & ~63));
         };
@@ -676,7 +691,7 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
         __syncthreads();
         for (int l0 = 0; l0 < n; l0 += 16) {
             // V rows l0 .. l0+15 of this chunk for the epilogue; G_il for this wave's rows
-            copy_rows(Vt, Vp, l0);
+            copy_rows(Vt, Vp, l0, std::integral_constant<int, 16>());
             if (cg >= 0 && cg < IB * 8) load16(Gq, 8u * (unsigned)((iblk * IB + (cg >> 3)) * np + l0 + 2 * (cg & 7)), Gil);
             dv4 acc[JB];
 #pragma unroll
@@ -699,8 +714,8 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
                 auto frag = [&](int ks, int s) {
                     const int kk = ks * 4 + lg;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) fa[s][r] = As[a_index(4 * r + (lane & 3), kk)];
-                    fv[s] = Vs[w * 16 + kk];
+                    for (int r = 0; r < 4; ++r) fa[s][r] = As[a_index<BK>(4 * r + (lane & 3), kk)];
+                    fv[s] = Vs[w * BK + kk];
 #pragma unroll
                     for (int jb = 0; jb < JB; ++jb) fb[s][jb] = Bs[kk * jw + jb * 16 + lc];
                 };
@@ -795,20 +810,23 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
                 for (int m = 0; m < DM; ++m)
                     if (lane + 64 * m < jw) d[m] = Ds[w * np + lane + 64 * m];
             } else {
+                // V tiles of DR rows, as many as one stage buffer holds
+                constexpr int DR = BK;
+                static_assert(DR * JW <= L::STAGE_EL, "a V tile must fit a stage buffer");
                 auto issue_v = [&](int l0, int buf) {
-                    copy<NT>(stage + buf * L::STAGE_EL, 8 * jw, tid, [&](int c) {
+                    copy<NT>(stage + buf * L::STAGE_EL, DR * (jw >> 1), tid, [&](int c) {
                         const int hp = jw >> 1, ll = c / hp, jp = c - ll * hp;
                         return Vp + (long)(l0 + ll) * np + j0 + 2 * jp;
                     });
                 };
                 issue_v(0, 0);
                 int b = 0;
-                for (int l0 = 0; l0 < n; l0 += 16, b ^= 1) {
+                for (int l0 = 0; l0 < n; l0 += DR, b ^= 1) {
                     wait_loads();
                     __syncthreads();
-                    if (l0 + 16 < n) issue_v(l0 + 16, b ^ 1);
+                    if (l0 + DR < n) issue_v(l0 + DR, b ^ 1);
                     const double* Vv = stage + b * L::STAGE_EL;
-                    for (int ll = 0; ll < 16; ++ll) {
+                    for (int ll = 0; ll < DR; ++ll) {
                         const double t = T1s[w * np + l0 + ll];      // zero beyond n
 #pragma unroll
                         for (int m = 0; m < DM; ++m)
@@ -850,14 +868,14 @@ __global__ __launch_bounds__(256) void k_pad_copy(int n, int np, long count, con
     }
 }
 
-template <int IB, int JB>
+template <int IB, int JB, int BK>
 __global__ __launch_bounds__(IB * 64, 2) void k_sigma2b_dma(int n, int np, int n_tau, int n_iblk, double sigma,
                                                             const double* __restrict__ Vp,
                                                             const double* __restrict__ Gp,
                                                             const double* __restrict__ G, double* __restrict__ Sc) {
     extern __shared__ __align__(16) double smem_d[];
     const long lb = xcd_remap(blockIdx.x, gridDim.x);
-    dma::tile<IB, JB>(n, np, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, Vp, Gp, G, Sc, smem_d);
+    dma::tile<IB, JB, BK>(n, np, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, Vp, Gp, G, Sc, smem_d);
 }
 
 // ---------------------------------------------------------------- float64 on the vector ALUs
@@ -1254,11 +1272,11 @@ constexpr int kNumCfg = 13;
 // float64 tile with direct-to-LDS staging: zero-padded copies of G and V in
 // context scratch (one pass each per call), then one workgroup per (slice pair,
 // block of IB rows i).
-template <int IB, int JB>
+template <int IB, int JB, int BK>
 int launch_dma_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, const double* G, double* Sc,
                    hipStream_t st) {
     const int np = (n + 15) & ~15;
-    const size_t smem = dma::Layout<IB, JB>::bytes(np);
+    const size_t smem = dma::Layout<IB, JB, BK>::bytes(np);
     if (smem > 160 * 1024) {
         set_error("n_b = %d too large for this Sigma-2B tile configuration's LDS budget", n);
         return NEGF_EINVAL;
@@ -1284,11 +1302,11 @@ int launch_dma_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, 
     NEGF_TRY(pad(V, Vp, 1));
     static bool attr_set = false;
     if (!attr_set) {
-        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b_dma<IB, JB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        HIP_TRY(hipFuncSetAttribute((const void*)k_sigma2b_dma<IB, JB, BK>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     160 * 1024));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sigma2b_dma<IB, JB>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, np, n_tau, n_iblk,
+    hipLaunchKernelGGL((k_sigma2b_dma<IB, JB, BK>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, np, n_tau, n_iblk,
                        (double)sigma, Vp, Gp, G, Sc);
     LAUNCH_CHECK();
     return NEGF_OK;
@@ -1385,8 +1403,8 @@ int launch(negf_ctx* ctx, int n, int n_tau, int sigma, const typename Cfg<MODE>:
                 if (cfg == 8) return launch_valu_cfg<8, 5, 1>(n, n_tau, sigma, Vd, Gd, Sd, st);
                 if (cfg == 9) return launch_valu_cfg<4, 5, 2>(n, n_tau, sigma, Vd, Gd, Sd, st);
                 if (cfg == 10) return launch_valu_cfg<4, 4, 2>(n, n_tau, sigma, Vd, Gd, Sd, st);
-                if (cfg == 11) return launch_dma_cfg<8, 13>(ctx, n, n_tau, sigma, Vd, Gd, Sd, st);
-                if (cfg == 12) return launch_dma_cfg<4, 13>(ctx, n, n_tau, sigma, Vd, Gd, Sd, st);
+                if (cfg == 11) return launch_dma_cfg<8, 13, 16>(ctx, n, n_tau, sigma, Vd, Gd, Sd, st);
+                if (cfg == 12) return launch_dma_cfg<4, 13, 4>(ctx, n, n_tau, sigma, Vd, Gd, Sd, st);
                 set_error("tile configuration %d is for float32 and bf16 only", cfg);
                 return NEGF_EINVAL;
             } else {
