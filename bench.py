@@ -36,9 +36,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "8538ee388b79f00e"
-TRAFFIC_F64_NB199 = {0: 656760591, 1: 657087079, 2: 656924007, 3: 657608886, 4: 657639620, 5: 1954087478,
-                     8: 663992569, 9: 665152955, 10: 663922478, 11: 827520557, 12: 1526072157}
+TRAFFIC_SRC_SHA256 = "19564aa016fc50d6"
+TRAFFIC_F64_NB199 = {0: 656758361, 1: 657163725, 2: 656923201, 3: 657693705, 4: 657741959, 5: 1949750072,
+                     8: 664495984, 9: 665658359, 10: 664416242, 11: 862481633, 12: 680571181}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):

@@ -366,11 +366,11 @@ typedef struct {
                                 NEGF_STOP_CONTRACTION (1): |d_k| rho / (1 - rho) < tol,
                                 d_k = E_k - E_(k-1), rho = max(|d_k / d_(k-1)|,
                                 |d_(k-1) / d_(k-2)|) < 1, k >= 3 (or d_k = 0): a bound
-                                on |E_k - E_inf| for a geometric tail. In the
+                                on |E_k - E_inf| for a geometric tail. The
                                 low-precision loop of the mixed form, whose
-                                energy changes reach the float32 noise, either
-                                rule ends that loop; the float64 refinement
-                                applies the chosen rule alone. */
+                                energy changes reach the float32 noise, also
+                                ends when |E_k - E_(k-1)| < tol/10; the float64
+                                refinement applies the chosen rule alone. */
     int guard;               /* 1: runaway guard (Sec. 3.1, stable N): if E_k or N_k is not
                                 finite, |N_k - n_elec| > n_elec / 2, or |dE| grew three
                                 times in a row, restart from G0 with alpha halved, at

@@ -508,12 +508,12 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
             // the mixed form has its own
             const double tol = (low && y.phase == PH_F64 && o->refine_tol > 0) ? o->refine_tol : o->tol;
             bool stop = false;
-            // the low-precision loop of the mixed form also ends on |dE| < tol:
-            // near the float32 noise the ratios of successive changes stop
+            // the low-precision loop of the mixed form also ends on |dE| < tol/10:
+            // at the float32 noise the ratios of successive changes stop
             // measuring the contraction, and the float64 refinement that
             // follows applies the chosen rule
             const bool hit = stop_test(o->stop_rule, y.dh, y.nd, tol) ||
-                             (y.phase == PH_LOW && stop_test(NEGF_STOP_DELTA, y.dh, y.nd, tol));
+                             (y.phase == PH_LOW && stop_test(NEGF_STOP_DELTA, y.dh, y.nd, 0.1 * tol));
             if (!fixed && y.k >= 1 && hit) {
                 y.conv = true;
                 stop = true;
