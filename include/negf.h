@@ -245,16 +245,8 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
  * float64 MFMA shape. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
-/* Sustained rate of the matrix-core operation the Sigma-2B kernels issue for
- * `dtype` (NEGF_F64: four-block 4x4x4 float64, NEGF_F32: 16x16x4 float32, NEGF_BF16:
- * 16x16x32 bf16 with float32 accumulation), measured on the context's GPU: a
- * kernel of 8 independent accumulator chains per wave with register operands,
- * 8 waves per SIMD on every compute unit, run twice (the faster run counts).
- * host out: tflops (TFLOP/s), clock_ghz (median shader clock of the waves,
- * from the core-clock and fixed-rate counters). A measured ceiling to quote
- * beside the datasheet peak; not part of the method. Uses context scratch
- * (a few MB). Synchronises. */
-int negf_matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* clock_ghz, void* stream);
+/* negf_matrix_rate, a measurement helper outside the method, is declared in
+ * negf_measure.h. */
 
 /* Sigma-2B (as negf_sigma2b) for `batch` systems of any sizes n_b[b] on one
  * tau grid of n_tau points, in a single persistent kernel launch: work items

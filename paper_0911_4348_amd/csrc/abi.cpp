@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.h"
+#include "negf_measure.h"
 
 namespace {
 thread_local std::string g_err;

@@ -2,6 +2,7 @@
 header declares is exported, the host FE-DVR setup and tau grids agree with
 the oracle, and invalid arguments are rejected before any device work."""
 import ctypes as C
+import glob
 import os
 import re
 
@@ -16,9 +17,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "negf.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -32,6 +35,7 @@ def L():
 def test_every_declared_symbol_is_exported(L):
     names = _declared()
     assert "negf_sigma2b" in names and "fedvr_build" in names and "negf_scf" in names
+    assert "negf_matrix_rate" in names                  # declared in negf_measure.h
     for name in names:
         assert hasattr(L, name), name
 
