@@ -10,6 +10,7 @@
 // ordering, run by one workgroup per matrix; from the second HF iteration on
 // it starts from the previous eigenvectors (F is then nearly diagonal in that
 // basis and a few sweeps suffice).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -335,6 +336,11 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
     const dim3 g2(grid_for(nn) > 256 ? 256 : grid_for(nn), B);
 
     // eigen-decomposition of the symmetric Mx (per system) into (eps, C); warm start from Cprev
+    // Jacobi tolerance on the relative off-diagonal norm: loose while the density
+    // still changes (an exact eigenbasis of a Fock matrix that is itself far from
+    // converged buys nothing), 1e-4 x the last density change once it is small,
+    // never tighter than 1e-15; the iterations that decide convergence run tight
+    double jac_tol = 1e-8;
     auto eig = [&](const double* Mx, const double* Cprev) -> int {
         if (Cprev) {
             // A = Cprev^T M Cprev, Vt = Cprev^T
@@ -348,7 +354,7 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
             hipLaunchKernelGGL(k_identity, g2, dim3(256), 0, st, n, nn, Vt);
             LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_jacobi, dim3(B), dim3(JAC_THREADS), jsm, st, n, nn, A, Vt, 60, 1e-15, dact);
+        hipLaunchKernelGGL(k_jacobi, dim3(B), dim3(JAC_THREADS), jsm, st, n, nn, A, Vt, 60, jac_tol, dact);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sort_eig, dim3(B), dim3(256), 0, st, n, nn, A, Vt, eps, C, dact);
         LAUNCH_CHECK();
@@ -378,6 +384,10 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
         HIP_TRY(hipMemcpyAsync(hres.data(), dres, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         bool changed = false;
+        double d_min = INFINITY;                   // smallest density change among active systems
+        for (int b = 0; b < B; ++b)
+            if (act[b]) d_min = std::min(d_min, hres[2 * b + 1]);
+        if (std::isfinite(d_min)) jac_tol = std::max(1e-15, std::min(1e-8, 1e-4 * d_min));
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
             E[b] = hres[2 * b];
