@@ -615,29 +615,57 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
 // registers. Both aggregates (forward and backward) come from one pass over the
 // registers, are folded in LDS, and the forward and backward output sweeps run
 // over the registers; only the final values are stored. Needs n_tau <= 32 CL.
-template <class T, int CL>
+//
+// With TL the workgroup first copies the table rows of its values of k (at most
+// two, since its 16 consecutive elements (k, j) span at most two rows when
+// n >= 16) into LDS, so the recurrences read them there instead of from the L2.
+template <class T, int CL, bool TL>
 __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T* __restrict__ In, T* __restrict__ Out,
                                                       const double* __restrict__ w, const double* __restrict__ hL,
-                                                      const double* __restrict__ hR, const double* __restrict__ Ea,
-                                                      const double* __restrict__ Eb, const double* __restrict__ dec,
+                                                      const double* __restrict__ hR, const double* __restrict__ Ea_g,
+                                                      const double* __restrict__ Eb_g, const double* __restrict__ dec_g,
                                                       const double* __restrict__ cpre,
                                                       const double* __restrict__ eps, double mu,
                                                       const double* __restrict__ C) {
     constexpr int NCH = 32, NE = 16;
     __shared__ double sdf[NCH][NE + 1], saf[NCH][NE + 1], sdb[NCH][NE + 1], sab[NCH][NE + 1];
+    extern __shared__ double tsm[];                  // TL: [2 rows][Ea, Eb, dec][n_tau]
     const int el = threadIdx.x & (NE - 1), ch = threadIdx.x / NE;
     const long nn = (long)n * n;
     const long e = (long)blockIdx.x * NE + el;
     const bool ok = e < nn;
     const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
     const bool pos = ok && eps[k] - mu >= 0.0;
-    const long tk = (long)k * n_tau;                 // row k of the k-major tables
     const double c = ok ? cpre[k] : 0.0;
     const int M = n_tau - 1, P = n_tau;
     const int p0 = (int)((long)ch * P / NCH), p1 = (int)((long)(ch + 1) * P / NCH);
     double b[CL], L[CL];
 #pragma unroll
     for (int t = 0; t < CL; ++t) b[t] = (ok && p0 + t < p1) ? (double)In[(long)(p0 + t) * nn + e] : 0.0;
+    const double *Ea, *Eb, *dec;
+    long tk;                                         // offset of row k in the tables read
+    if constexpr (TL) {
+        const long e0 = (long)blockIdx.x * NE;
+        const int k0 = (int)(e0 / n), k1 = (int)((e0 + NE - 1 < nn ? e0 + NE - 1 : nn - 1) / n);
+        for (int r = 0; r <= k1 - k0; ++r)
+            for (int q = threadIdx.x; q < n_tau; q += 512) {
+                const long g = (long)(k0 + r) * n_tau + q;
+                tsm[(3 * r + 0) * n_tau + q] = Ea_g[g];
+                tsm[(3 * r + 1) * n_tau + q] = Eb_g[g];
+                tsm[(3 * r + 2) * n_tau + q] = dec_g[g];
+            }
+        __syncthreads();
+        const double* row = tsm + 3 * (ok ? k - k0 : 0) * n_tau;
+        Ea = row;
+        Eb = row + n_tau;
+        dec = row + 2 * n_tau;
+        tk = 0;
+    } else {
+        Ea = Ea_g;
+        Eb = Eb_g;
+        dec = dec_g;
+        tk = (long)k * n_tau;                        // row k of the k-major tables
+    }
     // chunk aggregates: acc_out = d acc_in + a, forward (increasing p) and backward
     {
         double af = 0.0, df = 1.0, ab = 0.0, db = 1.0;
@@ -1050,12 +1078,27 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
     // G0 + Q[G0, I1] in the eigenbasis: In read once and Out written once where a
     // chunk of 32 fits in registers, else the chunked kernel that rereads In
     const unsigned sblk = (unsigned)((nn + 15) / 16);
-    if (n_tau <= 32 * 17)
-        hipLaunchKernelGGL((k_eig_scan_reg<T, 17>), dim3(sblk), dim3(512), 0, st, n, n_tau, It, I1, d_w, d_hL, d_hR, Ea,
-                           Eb, dec, cpre, eps, mu, C);
+    // n >= 16: the rows of the decay tables a workgroup needs (at most two) are
+    // staged in LDS, 6 n_tau doubles
+    const size_t tsm = n >= 16 ? sizeof(double) * 6 * (size_t)n_tau : 0;
+    auto scan_reg = [&](auto kern) -> int {
+        static bool attr = false;
+        if (!attr) {
+            HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+            attr = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(sblk), dim3(512), tsm, st, n, n_tau, It, I1, d_w, d_hL, d_hR, Ea, Eb, dec, cpre,
+                           eps, mu, C);
+        return NEGF_OK;
+    };
+    if (n_tau <= 32 * 17 && n >= 16)
+        NEGF_TRY(scan_reg(k_eig_scan_reg<T, 17, true>));
+    else if (n_tau <= 32 * 17)
+        NEGF_TRY(scan_reg(k_eig_scan_reg<T, 17, false>));
+    else if (n_tau <= 32 * 33 && n >= 16)
+        NEGF_TRY(scan_reg(k_eig_scan_reg<T, 33, true>));
     else if (n_tau <= 32 * 33)
-        hipLaunchKernelGGL((k_eig_scan_reg<T, 33>), dim3(sblk), dim3(512), 0, st, n, n_tau, It, I1, d_w, d_hL, d_hR, Ea,
-                           Eb, dec, cpre, eps, mu, C);
+        NEGF_TRY(scan_reg(k_eig_scan_reg<T, 33, false>));
     else
         hipLaunchKernelGGL((k_eig_scan_chunked<T>), dim3(sblk), dim3(256), 0, st, n, n_tau, It, I1, d_w, d_hL, d_hR,
                            Ea, Eb, dec, cpre, eps, mu, C);
