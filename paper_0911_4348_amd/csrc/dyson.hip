@@ -208,16 +208,26 @@ __device__ __forceinline__ void fft_twiddles(int M, int lds, const T* __restrict
 // of X [M+1][nc], with x^_0 = (X_0 - X_M)/2. Output planar [M/2][nc], written
 // as s A_k + D (s real; D real [nc], nullable, added to every real part).
 template <class T>
-__global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, int tw_lds, const T* __restrict__ X,
+__global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, int tw_lds, const T* X,
                                                  const T* __restrict__ twist, const T* __restrict__ tw, T osc,
-                                                 const T* __restrict__ oadd, T* __restrict__ Are,
-                                                 T* __restrict__ Aim) {
+                                                 const T* oadd, T* Are, T* Aim, long nblk1, const T* X2, T* Are2,
+                                                 T* Aim2) {
     extern __shared__ unsigned char sm_raw[];
     T* br = reinterpret_cast<T*>(sm_raw);
     T* bi = br + CW * M;
     const T *twr, *twi;
     fft_twiddles(M, tw_lds, tw, bi + CW * M, twr, twi);
-    const long c0 = (long)blockIdx.x * 2 * CW;
+    // workgroups from nblk1 on transform a second tensor X2 (plain, into Are2, Aim2)
+    long bx = blockIdx.x;
+    if (X2 && bx >= nblk1) {
+        bx -= nblk1;
+        X = X2;
+        Are = Are2;
+        Aim = Aim2;
+        osc = T(1);
+        oadd = nullptr;
+    }
+    const long c0 = bx * 2 * CW;
     // row q = 0 holds x^_0 = (X_0 - X_M) / 2 (twist factor 1)
     if (threadIdx.x < CW) {
         const int w = threadIdx.x;
@@ -949,7 +959,8 @@ int fft_tables(negf_ctx* ctx, int M, hipStream_t st, T** twist, T** tw) {
 
 template <class T>
 int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0, T* out1, const T* twist,
-               const T* tw, hipStream_t st, T oscale = T(1), const T* oadd = nullptr) {
+               const T* tw, hipStream_t st, T oscale = T(1), const T* oadd = nullptr, const T* in0b = nullptr,
+               T* out0b = nullptr, T* out1b = nullptr) {
     int L = 0;
     while ((1 << L) < M) ++L;
     // 64 KB of LDS for the columns of a workgroup (8 real columns in float64 at
@@ -972,8 +983,8 @@ int fft_launch(bool inverse, int nc, int M, const T* in0, const T* in1, T* out0,
         attr[ti][inverse] = true;
     }
     if (!inverse)
-        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, tw_lds, in0, twist,
-                           tw, oscale, oadd, out0, out1);
+        hipLaunchKernelGGL((k_fft_fwd<T>), dim3((unsigned)(in0b ? 2 * blocks : blocks)), dim3(threads), smem, st, nc, M,
+                           L, CW, tw_lds, in0, twist, tw, oscale, oadd, out0, out1, blocks, in0b, out0b, out1b);
     else
         hipLaunchKernelGGL((k_fft_inv<T>), dim3((unsigned)blocks), dim3(threads), smem, st, nc, M, L, CW, tw_lds, in0, in1,
                            twist, tw, out0);
@@ -1031,9 +1042,9 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
         NEGF_TRY(scratch_t(ctx, "dy_Cre", nn * nk, &Cre));
         NEGF_TRY(scratch_t(ctx, "dy_Cim", nn * nk, &Cim));
         NEGF_TRY(fft_tables<T>(ctx, M, st, &twist, &tw));
-        // A'_k = dtau A_k + St (St real, the same for every frequency), formed as the transform writes A_k
-        NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st, (T)dtau, St));
-        NEGF_TRY(fft_launch<T>(false, (int)nn, M, G_in, nullptr, Bre, Bim, twist, tw, st));
+        // A'_k = dtau A_k + St (St real, the same for every frequency), formed as the transform writes A_k;
+        // the transform of G in the same launch
+        NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st, (T)dtau, St, G_in, Bre, Bim));
         NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk));
         NEGF_TRY(fft_launch<T>(true, (int)nn, M, Cre, Cim, I1, nullptr, twist, tw, st));
         // end points p = 0 and p = M
