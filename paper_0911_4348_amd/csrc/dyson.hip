@@ -110,19 +110,32 @@ __device__ double block_csum(CSum v, double* red) {
 
 
 // ------------------------------------------------------------ St = Sigma^HF[-G_M] - Sigma0
+// (with Lm, Rm given, also the end-point matrices of the Fourier route)
 template <class T>
-__global__ void k_sigma_tilde(int n, int sigma, const double* __restrict__ V, const T* __restrict__ GM,
-                              const double* __restrict__ Sigma0, T* __restrict__ St) {
-    const long nn = (long)n * n;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        double s = V[e] * (double)GM[e];                 // -V_ij rho_ij with rho = -G_M
-        if (i == j) {
-            double h = 0.0;
-            for (int k = 0; k < n; ++k) h -= V[(long)i * n + k] * (double)GM[(long)k * n + k];
-            s += sigma * h;
+__global__ __launch_bounds__(256) void k_sigma_tilde(int n, int sigma, const double* __restrict__ V,
+                                                     const T* __restrict__ GM, const double* __restrict__ Sigma0,
+                                                     T* __restrict__ St, T dtau, const T* __restrict__ Sc0,
+                                                     const T* __restrict__ ScM, const T* __restrict__ G0,
+                                                     T* __restrict__ Lm, T* __restrict__ Rm) {
+    __shared__ double red[2 * 4 + 2];
+    const int i = blockIdx.x;                           // one workgroup per row
+    if (i >= n) return;
+    const long r = (long)i * n;
+    // Hartree term of row i: sum over k of V_ik rho_kk, rho = -G_M
+    CSum hs{0.0, 0.0};
+    for (int k = threadIdx.x; k < n; k += 256) hs.add(-V[r + k] * (double)GM[(long)k * n + k]);
+    const double h = block_csum<256>(hs, red);
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const long e = r + j;
+        double s = V[e] * (double)GM[e];                 // -V_ij rho_ij
+        if (j == i) s += sigma * h;
+        const T stv = (T)(s - Sigma0[e]);
+        St[e] = stv;
+        if (Lm) {
+            // end-point matrices of the Fourier route: L = St/2 - dtau (Sc_0 + Sc_M)/4, R = G_0 + G_M
+            Lm[e] = T(0.5) * stv - T(0.25) * dtau * (Sc0[e] + ScM[e]);
+            Rm[e] = G0[e] + GM[e];
         }
-        St[e] = (T)(s - Sigma0[e]);
     }
 }
 
@@ -315,16 +328,6 @@ __global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, 
         const T cr = twist[2 * q], ci = twist[2 * q + 1];          // e^(-i pi q/M); multiply by its conjugate
         if (c1 < nc) out[(long)q * nc + c1] = yr * cr + yi * ci;
         if (c2 < nc) out[(long)q * nc + c2] = yi * cr - yr * ci;
-    }
-}
-
-// L = St/2 - dtau/4 (Sc_0 + Sc_M), R = G_0 + G_M
-template <class T>
-__global__ void k_endpoint_prep(long nn, T dtau, const T* St, const T* Sc0, const T* ScM, const T* G0,
-                                const T* GM, T* Lm, T* Rm) {
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
-        Lm[e] = T(0.5) * St[e] - T(0.25) * dtau * (Sc0[e] + ScM[e]);
-        Rm[e] = G0[e] + GM[e];
     }
 }
 
@@ -1023,12 +1026,17 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
     const double* d_hL = d_tau + 2 * n_tau;
     const double* d_hR = d_tau + 3 * n_tau;
 
-    T *St, *I1, *It;
-    NEGF_TRY(scratch_t(ctx, "dy_St", nn, &St));
+    // LS = [Lm | St] and ER = [Em | SR]: the two end-point products L R and St R in one batched launch
+    T *LS, *ER, *Rm, *I1, *It;
+    NEGF_TRY(scratch_t(ctx, "dy_LS", 2 * nn, &LS));
+    NEGF_TRY(scratch_t(ctx, "dy_ER", 2 * nn, &ER));
+    NEGF_TRY(scratch_t(ctx, "dy_Rm", nn, &Rm));
     NEGF_TRY(scratch_t(ctx, "dy_I1", nn * n_tau, &I1));
     NEGF_TRY(scratch_t(ctx, "dy_It", nn * n_tau, &It));
-    hipLaunchKernelGGL((k_sigma_tilde<T>), dim3(grid_for(nn)), dim3(256), 0, st, n, sigma, V,
-                       G_in + (long)M * nn, Sigma0, St);
+    T* const St = LS + nn;
+    hipLaunchKernelGGL((k_sigma_tilde<T>), dim3((unsigned)std::max(n, 1)), dim3(256), 0, st, n, sigma, V,
+                       G_in + (long)M * nn, Sigma0, St, (T)dtau, Sc, Sc + (long)M * nn, G_in,
+                       use_fft ? LS : nullptr, Rm);
     LAUNCH_CHECK();
 
     // ---------------- I1 = St G + Q[Sigma_c, G]
@@ -1047,18 +1055,9 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
         NEGF_TRY(fft_launch<T>(false, (int)nn, M, Sc, nullptr, Are, Aim, twist, tw, st, (T)dtau, St, G_in, Bre, Bim));
         NEGF_TRY(cgemm<T>(st, n, Are, Aim, Bre, Bim, Cre, Cim, nn, nk));
         NEGF_TRY(fft_launch<T>(true, (int)nn, M, Cre, Cim, I1, nullptr, twist, tw, st));
-        // end points p = 0 and p = M
-        T *Lm, *Rm, *Em, *SR;
-        NEGF_TRY(scratch_t(ctx, "dy_Lm", nn, &Lm));
-        NEGF_TRY(scratch_t(ctx, "dy_Rm", nn, &Rm));
-        NEGF_TRY(scratch_t(ctx, "dy_Em", nn, &Em));
-        NEGF_TRY(scratch_t(ctx, "dy_SR", nn, &SR));
-        hipLaunchKernelGGL((k_endpoint_prep<T>), dim3(grid_for(nn)), dim3(256), 0, st, nn, (T)dtau, St, Sc,
-                           Sc + (long)M * nn, G_in, G_in + (long)M * nn, Lm, Rm);
-        LAUNCH_CHECK();
-        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), Lm, n, 0, Rm, n, 0, T(0), nullptr, 0, 0, Em, n, 0, 1));
-        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), St, n, 0, Rm, n, 0, T(0), nullptr, 0, 0, SR, n, 0, 1));
-        hipLaunchKernelGGL((k_endpoint_final<T>), dim3(grid_for(nn)), dim3(256), 0, st, nn, Em, SR, I1,
+        // end points p = 0 and p = M: Em = L R, SR = St R
+        NEGF_TRY(gemm<T>(st, false, false, n, n, n, T(1), LS, n, nn, Rm, n, 0, T(0), nullptr, 0, 0, ER, n, nn, 2));
+        hipLaunchKernelGGL((k_endpoint_final<T>), dim3(grid_for(nn)), dim3(256), 0, st, nn, ER, ER + nn, I1,
                            I1 + (long)M * nn);
         LAUNCH_CHECK();
     } else {
