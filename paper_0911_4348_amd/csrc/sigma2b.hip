@@ -600,7 +600,8 @@ __device__ __forceinline__ void wait_loads() { asm volatile("s_waitcnt vmcnt(0)"
 template <int IB, int JB, int BK>
 __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int iblk, double sigma,
                                      const double* __restrict__ Vp, const double* __restrict__ Gp,
-                                     const double* __restrict__ G, double* __restrict__ Sc, double* smem) {
+                                     const double* __restrict__ G, double* __restrict__ Sc, double* smem, int lbeg,
+                                     int lend, double* __restrict__ pd, double* __restrict__ px) {
     typedef Layout<IB, JB, BK> L;
     constexpr int NT = IB * 64;
     constexpr int JW = L::JW;
@@ -686,10 +687,10 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
             if (offv != kNone) load16(Vp, offv + 8u * (unsigned)k0, sb + L::B_EL + L::A_EL + 2 * (cv & ~63));
         };
         int g = 0;                                   // panels started in this chunk
-        issue(0, 0, 0);
+        issue(lbeg, 0, 0);
         wait_loads();
         __syncthreads();
-        for (int l0 = 0; l0 < n; l0 += 16) {
+        for (int l0 = lbeg; l0 < lend; l0 += 16) {
             // V rows l0 .. l0+15 of this chunk for the epilogue; G_il for this wave's rows
             copy_rows(Vt, Vp, l0, std::integral_constant<int, 16>());
             if (cg >= 0 && cg < IB * 8) load16(Gq, 8u * (unsigned)((iblk * IB + (cg >> 3)) * np + l0 + 2 * (cg & 7)), Gil);
@@ -700,7 +701,7 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
             for (int pn = 0; pn < npan; ++pn, ++g) {
                 const int cur = g & 1;
                 if (pn + 1 < npan) issue(l0, pn + 1, cur ^ 1);
-                else if (l0 + 16 < n) issue(l0 + 16, 0, cur ^ 1);
+                else if (l0 + 16 < lend) issue(l0 + 16, 0, cur ^ 1);
                 const double* Bs = stage + cur * L::STAGE_EL;
                 const double* As = Bs + L::B_EL;
                 const double* Vs = As + L::A_EL;
@@ -834,7 +835,18 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
                     }
                 }
             }
-            if (i < n) {
+            if (i < n && px) {
+                // one part of the l range: D and X of this part, summed over
+                // the parts by k_s2b_parts_sum
+#pragma unroll
+                for (int m = 0; m < DM; ++m) {
+                    const int j = j0 + lane + 64 * m;
+                    if (lane + 64 * m < jw && j < n) {
+                        pd[(long)i * np + j] = d[m];
+                        px[(long)i * np + j] = Xs[w * np + j];
+                    }
+                }
+            } else if (i < n) {
                 // G_ij of slice q from the padded copy (its rows were streamed
                 // through the L2 by the panels just before), of slice q' from
                 // the row already in LDS
@@ -868,14 +880,54 @@ __global__ __launch_bounds__(256) void k_pad_copy(int n, int np, long count, con
     }
 }
 
+// Workgroups below n_full take one (slice pair, i-block) each. With n_parts > 0
+// the middle slice (tau = beta/2, paired with itself, the last pair) is left out
+// of them: it would be the last round of the launch, with most CUs idle. The
+// n_parts x n_iblk workgroups after n_full take it instead, each one part of its
+// l-tiles, and write their D and X terms to part (n_parts blocks of
+// [D | X], each [n_iblk IB][np]).
 template <int IB, int JB, int BK>
 __global__ __launch_bounds__(IB * 64, 2) void k_sigma2b_dma(int n, int np, int n_tau, int n_iblk, double sigma,
                                                             const double* __restrict__ Vp,
                                                             const double* __restrict__ Gp,
-                                                            const double* __restrict__ G, double* __restrict__ Sc) {
+                                                            const double* __restrict__ G, double* __restrict__ Sc,
+                                                            long n_full, int n_parts, double* __restrict__ part) {
     extern __shared__ __align__(16) double smem_d[];
-    const long lb = xcd_remap(blockIdx.x, gridDim.x);
-    dma::tile<IB, JB, BK>(n, np, n_tau, (int)(lb / n_iblk), (int)(lb % n_iblk), sigma, Vp, Gp, G, Sc, smem_d);
+    const long b = blockIdx.x;
+    int pair, iblk, lbeg = 0, lend = n;
+    double *pd = nullptr, *px = nullptr;
+    if (b < n_full) {
+        const long lb = xcd_remap(b, n_full);
+        pair = (int)(lb / n_iblk);
+        iblk = (int)(lb % n_iblk);
+    } else {
+        const int u = (int)(b - n_full), sp = u / n_iblk;
+        const int nlt = (n + 15) >> 4;
+        const long ni = (long)n_iblk * IB * np;
+        pair = (n_tau - 1) / 2;
+        iblk = u - sp * n_iblk;
+        lbeg = 16 * (sp * nlt / n_parts);
+        lend = min(n, 16 * ((sp + 1) * nlt / n_parts));
+        pd = part + 2 * ni * sp;
+        px = pd + ni;
+    }
+    dma::tile<IB, JB, BK>(n, np, n_tau, pair, iblk, sigma, Vp, Gp, G, Sc, smem_d, lbeg, lend, pd, px);
+}
+
+// Sigma_c of the middle slice from the parts: sigma G_ij sum D - sum X
+__global__ void k_s2b_parts_sum(int n, int np, long ni, int n_parts, double sigma, const double* __restrict__ Gm,
+                                const double* __restrict__ part, double* __restrict__ Sm) {
+    const long nn = (long)n * n;
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < nn; e += (long)gridDim.x * 256) {
+        const int i = (int)(e / n), j = (int)(e - (long)i * n);
+        const long o = (long)i * np + j;
+        double d = 0.0, x = 0.0;
+        for (int sp = 0; sp < n_parts; ++sp) {
+            d += part[2 * ni * sp + o];
+            x += part[2 * ni * sp + ni + o];
+        }
+        Sm[e] = sigma * Gm[e] * d - x;
+    }
 }
 
 // ---------------------------------------------------------------- float64 on the vector ALUs
@@ -1283,11 +1335,17 @@ int launch_dma_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, 
     }
     const int n_pairs = (n_tau + 1) / 2;
     const int n_iblk = (n + IB - 1) / IB;
-    const long blocks = (long)n_pairs * n_iblk;
+    // an odd n_tau has a middle slice: split over up to 8 parts of its l-tiles
+    const int n_parts = (n_tau & 1) && n_pairs >= 2 ? std::min(8, (n + 15) / 16) : 0;
+    const long n_full = (long)(n_parts ? n_pairs - 1 : n_pairs) * n_iblk;
+    const long blocks = n_full + (long)n_parts * n_iblk;
     if (blocks > 0x7fffffffL) {
         set_error("too many workgroups");
         return NEGF_EINVAL;
     }
+    const long ni = (long)n_iblk * IB * np;
+    double* part = nullptr;
+    if (n_parts) NEGF_TRY(scratch_t(ctx, "s2b_parts", (size_t)2 * ni * n_parts, &part));
     double *Gp = nullptr, *Vp = nullptr;
     NEGF_TRY(scratch_t(ctx, "s2b_gpad", (size_t)n_tau * np * np, &Gp));
     NEGF_TRY(scratch_t(ctx, "s2b_vpad", (size_t)np * np, &Vp));
@@ -1307,8 +1365,14 @@ int launch_dma_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, 
         attr_set = true;
     }
     hipLaunchKernelGGL((k_sigma2b_dma<IB, JB, BK>), dim3((unsigned)blocks), dim3(IB * 64), smem, st, n, np, n_tau, n_iblk,
-                       (double)sigma, Vp, Gp, G, Sc);
+                       (double)sigma, Vp, Gp, G, Sc, n_full, n_parts, part);
     LAUNCH_CHECK();
+    if (n_parts) {
+        const long q = (n_tau - 1) / 2, nn = (long)n * n;
+        hipLaunchKernelGGL(k_s2b_parts_sum, dim3((unsigned)std::min<long>((nn + 255) / 256, 4096)), dim3(256), 0, st, n,
+                           np, ni, n_parts, (double)sigma, G + q * nn, part, Sc + q * nn);
+        LAUNCH_CHECK();
+    }
     return NEGF_OK;
 }
 
