@@ -697,6 +697,7 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
             dv4 acc[JB];
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb) acc[jb] = Mma<double>::zero();
+            const int nrg = min(4, (n - l0 + 3) >> 2);   // groups of 4 rows l holding l < n
 #pragma unroll 1
             for (int pn = 0; pn < npan; ++pn, ++g) {
                 const int cur = g & 1;
@@ -720,19 +721,27 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
 #pragma unroll
                     for (int jb = 0; jb < JB; ++jb) fb[s][jb] = Bs[kk * jw + jb * 16 + lc];
                 };
+                // k-steps of the last panel past k = n and row groups of the
+                // last l-tile past l = n hold zero padding only: skipped
+                // (uniform branches; the results are the same)
+                const int nks = min(BK / 4, (n - pn * BK + 3) >> 2);
                 frag(0, 0);
 #pragma unroll
                 for (int ks = 0; ks < BK / 4; ++ks) {
                     const int s = ks & 1;
                     if (ks + 1 < BK / 4) frag(ks + 1, s ^ 1);
-                    double a[4];
+                    if (ks == 0 || ks < nks) {
+                        double a[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) a[r] = fa[s][r] * fv[s];
+                        for (int r = 0; r < 4; ++r) a[r] = fa[s][r] * fv[s];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
+                        for (int r = 0; r < 4; ++r)
+                            if (r == 0 || r < nrg)
 #pragma unroll
-                        for (int jb = 0; jb < JB; ++jb)
-                            acc[jb][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[r], fb[s][jb], acc[jb][r], 0, 0, 0);
+                                for (int jb = 0; jb < JB; ++jb)
+                                    acc[jb][r] =
+                                        __builtin_amdgcn_mfma_f64_4x4x4f64(a[r], fb[s][jb], acc[jb][r], 0, 0, 0);
+                    }
                 }
                 wait_loads();
                 __syncthreads();
