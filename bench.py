@@ -36,9 +36,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "19564aa016fc50d6"
-TRAFFIC_F64_NB199 = {0: 656758361, 1: 657163725, 2: 656923201, 3: 657693705, 4: 657741959, 5: 1949750072,
-                     8: 664495984, 9: 665658359, 10: 664416242, 11: 862481633, 12: 680571181}
+TRAFFIC_SRC_SHA256 = "f6add80b3bd24cc9"
+TRAFFIC_F64_NB199 = {0: 656775671, 1: 657093108, 2: 656921231, 3: 657573752, 4: 657644871, 5: 1953808911,
+                     8: 663828924, 9: 664908269, 10: 663835326, 11: 871589318, 12: 683065387}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):

@@ -878,14 +878,23 @@ __device__ __forceinline__ void tile(int n, int np, int n_tau, int pair, int ibl
 
 }  // namespace dma
 
-// Zero-padded copy of a stack of n x n matrices into np x np blocks.
+// Zero-padded copy of a stack of n x n matrices into np x np blocks (np a
+// multiple of 16): grid y runs over the matrices, and each thread writes two
+// adjacent padded elements with one 16-byte store (32-bit index arithmetic
+// within a matrix).
 __global__ __launch_bounds__(256) void k_pad_copy(int n, int np, long count, const double* __restrict__ src,
                                                   double* __restrict__ dst) {
-    const long pp = (long)np * np;
-    for (long e = blockIdx.x * 256L + threadIdx.x; e < count * pp; e += (long)gridDim.x * 256) {
-        const long s = e / pp, rc = e - s * pp;
-        const int r = (int)(rc / np), c = (int)(rc - (long)r * np);
-        dst[e] = (r < n && c < n) ? src[s * n * n + (long)r * n + c] : 0.0;
+    const int hp = np * np / 2;
+    for (long s = blockIdx.y; s < count; s += gridDim.y) {
+        const double* a = src + s * n * n;
+        double2* b = reinterpret_cast<double2*>(dst + s * np * np);
+        for (int e = blockIdx.x * 256 + threadIdx.x; e < hp; e += gridDim.x * 256) {
+            const int r = 2 * e / np, c = 2 * e - r * np;
+            double2 v;
+            v.x = (r < n && c < n) ? a[r * n + c] : 0.0;
+            v.y = (r < n && c + 1 < n) ? a[r * n + c + 1] : 0.0;
+            b[e] = v;
+        }
     }
 }
 
@@ -940,9 +949,9 @@ __global__ void k_s2b_parts_sum(int n, int np, long ni, int n_parts, double sigm
 }
 
 // ---------------------------------------------------------------- float64 on the vector ALUs
-// On gfx950 the float64 vector FMA sustains far more than the float64 matrix
-// cores (measured: ~72 vs ~48 TFLOP/s), so the float64 mode also has tiles that
-// form M^(i) with plain FMAs. A wave still owns one i; its 64 lanes form an 8 x 8
+// On gfx950 the float64 vector FMA sustains more than the 16x16x4 float64 matrix
+// instruction (measured: ~72 vs ~48 TFLOP/s; the four-block 4x4x4 form reaches
+// ~75), so the float64 mode also has tiles that form M^(i) with plain FMAs. A wave still owns one i; its 64 lanes form an 8 x 8
 // grid and lane (ty, tx) accumulates a TL x TL block of a HT x HT tile of M^(i)
 // (HT = 8 TL), rows l = l0 + ty TL + a, columns j = j0 + tx TL + b. The k-panels
 // of Gb (rows l) and G (columns j) are staged in LDS (shared by the IB waves);
@@ -1359,9 +1368,10 @@ int launch_dma_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, 
     NEGF_TRY(scratch_t(ctx, "s2b_gpad", (size_t)n_tau * np * np, &Gp));
     NEGF_TRY(scratch_t(ctx, "s2b_vpad", (size_t)np * np, &Vp));
     auto pad = [&](const double* src, double* dst, long count) -> int {
-        long b = (count * np * np + 255) / 256;
-        if (b > 65536) b = 65536;
-        hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)b), dim3(256), 0, st, n, np, count, src, dst);
+        if (count <= 0) return NEGF_OK;
+        const unsigned bx = (unsigned)std::min<long>(((long)np * np / 2 + 255) / 256, 1024);
+        const unsigned by = (unsigned)std::min<long>(count, 65535);
+        hipLaunchKernelGGL(k_pad_copy, dim3(bx, by), dim3(256), 0, st, n, np, count, src, dst);
         LAUNCH_CHECK();
         return NEGF_OK;
     };
