@@ -140,6 +140,15 @@ __global__ __launch_bounds__(256) void k_sigma_tilde(int n, int sigma, const dou
 }
 
 // ------------------------------------------------------------ FFT in LDS
+// Workgroups are dealt to the 8 XCDs round-robin by block index; renumbered so
+// that each XCD takes a contiguous range, neighbouring column groups (which
+// share 128-byte lines of every row) run under the same L2 instead of each
+// XCD fetching the whole line for its half.
+__device__ __forceinline__ long xcd_block(long b, long nb) {
+    const long x = b & 7, k = b >> 3;
+    return x * (nb >> 3) + (x < (nb & 7) ? x : (nb & 7)) + k;
+}
+
 constexpr int FFT_UNR = 8;   // loads of a thread in flight at once when filling LDS
 
 __device__ __forceinline__ int bitrev(int x, int L) { return (int)(__brev((unsigned)x) >> (32 - L)); }
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(1024) void k_fft_fwd(int nc, int M, int L, int CW, 
     const T *twr, *twi;
     fft_twiddles(M, tw_lds, tw, bi + CW * M, twr, twi);
     // workgroups from nblk1 on transform a second tensor X2 (plain, into Are2, Aim2)
-    long bx = blockIdx.x;
+    long bx = xcd_block(blockIdx.x, gridDim.x);
     if (X2 && bx >= nblk1) {
         bx -= nblk1;
         X = X2;
@@ -304,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_fft_inv(int nc, int M, int L, int CW, 
     T* bi = br + CW * M;
     const T *twr, *twi;
     fft_twiddles(M, tw_lds, tw, bi + CW * M, twr, twi);
-    const long c0 = (long)blockIdx.x * 2 * CW;
+    const long c0 = xcd_block(blockIdx.x, gridDim.x) * 2 * CW;
     for (int idx = threadIdx.x; idx < (M >> 1) * CW; idx += blockDim.x) {
         const int k = idx / CW, w = idx % CW;
         const long c1 = c0 + 2 * w, c2 = c1 + 1;
@@ -531,7 +540,7 @@ __global__ __launch_bounds__(256) void k_eig_scan_chunked(int n, int n_tau, cons
     __shared__ double sd[NCH][NE + 1], sa[NCH][NE + 1];
     const int el = threadIdx.x & (NE - 1), ch = threadIdx.x / NE;
     const long nn = (long)n * n;
-    const long e = (long)blockIdx.x * NE + el;
+    const long e = xcd_block(blockIdx.x, gridDim.x) * NE + el;   // XCD-contiguous, as in the transforms
     const bool ok = e < nn;
     const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
     const bool pos = ok && eps[k] - mu >= 0.0;
@@ -645,7 +654,7 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
     extern __shared__ double tsm[];                  // TL: [2 rows][Ea, Eb, dec][n_tau]
     const int el = threadIdx.x & (NE - 1), ch = threadIdx.x / NE;
     const long nn = (long)n * n;
-    const long e = (long)blockIdx.x * NE + el;
+    const long e = xcd_block(blockIdx.x, gridDim.x) * NE + el;   // XCD-contiguous, as in the transforms
     const bool ok = e < nn;
     const int k = ok ? (int)(e / n) : 0, j = ok ? (int)(e % n) : 0;
     const bool pos = ok && eps[k] - mu >= 0.0;
@@ -658,7 +667,7 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
     const double *Ea, *Eb, *dec;
     long tk;                                         // offset of row k in the tables read
     if constexpr (TL) {
-        const long e0 = (long)blockIdx.x * NE;
+        const long e0 = xcd_block(blockIdx.x, gridDim.x) * NE;
         const int k0 = (int)(e0 / n), k1 = (int)((e0 + NE - 1 < nn ? e0 + NE - 1 : nn - 1) / n);
         for (int r = 0; r <= k1 - k0; ++r)
             for (int q = threadIdx.x; q < n_tau; q += 512) {
@@ -766,16 +775,20 @@ __global__ __launch_bounds__(512) void k_eig_scan_reg(int n, int n_tau, const T*
 // I <= J: both tiles are read row-wise into LDS and written back row-wise.
 // grid.x = tile pair, grid.y = slice.
 template <class T>
-__global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, T* G) {
+__global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, int npair, T* G) {
     __shared__ T A[32][33], B[32][33];
-    // tile pair index -> (I, J), I <= J, row-major over the upper triangle of tiles
-    int r = blockIdx.x, I = 0;
+    // one workgroup per (slice, tile pair), XCD-contiguous so that the tiles of a
+    // slice, which share the lines at their edges, run under one L2; tile pair
+    // index -> (I, J), I <= J, row-major over the upper triangle of tiles
+    const long lbk = xcd_block(blockIdx.x, gridDim.x);
+    const long sl = lbk / npair;
+    int r = (int)(lbk - sl * npair), I = 0;
     while (r >= nt - I) {
         r -= nt - I;
         ++I;
     }
     const int J = I + r;
-    T* g = G + (long)blockIdx.y * n * n;
+    T* g = G + sl * n * n;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int yy = ty; yy < 32; yy += 8) {
         const int ra = I * 32 + yy, ca = J * 32 + tx;
@@ -802,11 +815,14 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int nt, T* G) {
 // first of them is summed. Tr[Sc(beta - tau_q) G(tau_q)] = sum_I part[q][I].
 constexpr int EN_MAXJ = 4;                             // blocks of a strip whose loads are in flight together
 template <class T>
-__global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T* __restrict__ Sc,
+__global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, int nI, const T* __restrict__ Sc,
                                                        const T* __restrict__ G, double* part) {
     __shared__ double red[2 * (256 / 64) + 2];
     __shared__ double gt[32][33];
-    const int q = blockIdx.x, I = 32 * blockIdx.y, nI = gridDim.y;
+    // XCD-contiguous: the strips of a slice read G at neighbouring columns of
+    // every row, and run under one L2
+    const long lbk = xcd_block(blockIdx.x, gridDim.x);
+    const int q = (int)(lbk / nI), yb = (int)(lbk - (long)q * nI), I = 32 * yb;
     const long nn = (long)n * n;
     const T* S = Sc + (long)(n_tau - 1 - q) * nn;
     const T* g = G + (long)q * nn;
@@ -843,8 +859,8 @@ __global__ __launch_bounds__(256) void k_energy_slices(int n, int n_tau, const T
     }
     const CSum tot = block_csum_pair<256>(s, red);
     if (threadIdx.x == 0) {
-        part[2 * ((long)q * nI + blockIdx.y)] = tot.s;
-        part[2 * ((long)q * nI + blockIdx.y) + 1] = tot.c;
+        part[2 * ((long)q * nI + yb)] = tot.s;
+        part[2 * ((long)q * nI + yb) + 1] = tot.c;
     }
 }
 
@@ -1115,15 +1131,15 @@ int dyson_run(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, const 
     LAUNCH_CHECK();
     NEGF_TRY(gemm<T>(st, false, false, n, n, n, (T)alpha, Ct, n, 0, I1, n, nn, (T)(1.0 - alpha), G_in, n, nn, G_out,
                      n, nn, n_tau));
-    if (symmetrize) {
-        const int nt = (n + 31) / 32;
-        for (int s0 = 0; s0 < n_tau; s0 += 65535) {
-            const int ns = min(65535, n_tau - s0);
-            hipLaunchKernelGGL((k_symmetrize<T>), dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)ns), dim3(256), 0, st,
-                               n, nt, G_out + (long)s0 * nn);
+    if (symmetrize && n > 0) {
+        const int nt = (n + 31) / 32, npair = nt * (nt + 1) / 2;
+        const int chunk = (int)std::min<long>(n_tau, 0x7fffffffL / npair);
+        for (int s0 = 0; s0 < n_tau; s0 += chunk) {
+            const int ns = min(chunk, n_tau - s0);
+            hipLaunchKernelGGL((k_symmetrize<T>), dim3((unsigned)((long)npair * ns)), dim3(256), 0, st, n, nt, npair,
+                               G_out + (long)s0 * nn);
             LAUNCH_CHECK();
         }
-        LAUNCH_CHECK();
     }
     return NEGF_OK;
 }
@@ -1142,7 +1158,8 @@ int energy_launch(negf_ctx* ctx, const negf_tau_grid_t* tg, int n, int sigma, co
     const int nI = (n + 31) / 32;
     // sized for n up to 1024 at once, so that systems of a batch share one buffer
     NEGF_TRY(scratch_t(ctx, "en_part", (size_t)2 * n_tau * std::max(nI, 32), &part));
-    hipLaunchKernelGGL((k_energy_slices<T>), dim3(n_tau, nI), dim3(256), 0, st, n, n_tau, Sc, G, part);
+    hipLaunchKernelGGL((k_energy_slices<T>), dim3((unsigned)((long)n_tau * nI)), dim3(256), 0, st, n, n_tau, nI, Sc, G,
+                       part);
     LAUNCH_CHECK();
     double* rowpart;
     // sized for n up to 1024 at once, so that systems of a batch share one buffer
