@@ -298,6 +298,17 @@ def run_scan(args, torch, negf, W):
     ctx.close()
 
 
+def run_issue_probe(negf):
+    """Whether float64 vector FMAs add throughput beside the float64 MFMAs: the time of
+    mixed register-only loops against the times of their parts."""
+    ctx = negf.Context(0)
+    print("MFMA chains, FMA chains: ms, MFMA TFLOP/s, FMA TFLOP/s, total TFLOP/s", flush=True)
+    for nm, nv in ((8, 0), (0, 8), (0, 32), (8, 2), (8, 4), (8, 8), (8, 16), (8, 32)):
+        ms, tm, tv = negf.f64_issue_probe(ctx, nm, nv)
+        print(f"{nm:2d} {nv:2d}: {ms:8.3f} ms  {tm:6.2f}  {tv:6.2f}  {tm + tv:6.2f}", flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +335,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed region, run one elementwise float64 copy of BYTES "
                          "(reads BYTES, writes BYTES) to calibrate HBM byte counters")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="instead of the benchmark, time register-only loops of float64 MFMA and vector-FMA "
+                         "chains (negf_f64_issue_probe) and print one line per combination")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library runs the hot path on a single MI355X "
@@ -335,6 +349,8 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.issue_probe:
+        return run_issue_probe(negf)
     if args.workload == "scan":
         return run_scan(args, torch, negf, W)
     if args.workload == "h3p":

@@ -114,6 +114,7 @@ _SIGS = {
     "negf_sigma2b_batched_tune": (C.c_int, [_VP, C.c_int, _IP, C.c_int, _IP, _VP, _VP, _VP, C.c_int, C.c_int,
                                             _IP, _DP, _VP]),
     "negf_matrix_rate": (C.c_int, [_VP, C.c_int, _DP, _DP, _VP]),
+    "negf_f64_issue_probe": (C.c_int, [_VP, C.c_int, C.c_int, _DP, _DP, _DP, _VP]),
     "negf_mlp_param_count": (C.c_int, [_IP]),
     "negf_mlp_features": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int, _DP, _DP, C.c_int, _VP, C.c_double,
                                     C.c_int, _VP, _VP, _VP, _VP, _VP]),
@@ -517,6 +518,15 @@ def matrix_rate(ctx: Context, dtype="f64", stream=None):
     ghz = C.c_double(0.0)
     _check(lib().negf_matrix_rate(ctx.handle, _DT[dtype], C.byref(tf), C.byref(ghz), _stream(stream)))
     return tf.value, ghz.value
+
+
+def f64_issue_probe(ctx: Context, n_mfma, n_fma, stream=None):
+    """negf_f64_issue_probe: (ms, MFMA TFLOP/s, vector-FMA TFLOP/s) of a register-only
+    loop with n_mfma float64 MFMA chains and n_fma float64 FMA chains per wave."""
+    ms, tm, tv = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+    _check(lib().negf_f64_issue_probe(ctx.handle, int(n_mfma), int(n_fma), C.byref(ms), C.byref(tm), C.byref(tv),
+                                      _stream(stream)))
+    return ms.value, tm.value, tv.value
 
 
 def sigma2b_batched(ctx: Context, Vs, Gs, sigma, dtype="f64", outs=None, stream=None):

@@ -582,6 +582,15 @@ extern "C" int negf_matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double
     return matrix_rate(ctx, dtype, tflops, clock_ghz, (hipStream_t)stream);
 }
 
+extern "C" int negf_f64_issue_probe(negf_ctx* ctx, int n_mfma, int n_fma, double* ms, double* mfma_tflops,
+                                    double* fma_tflops, void* stream) {
+    NEGF_REQUIRE(ctx, "ctx is NULL");
+    NEGF_REQUIRE(ms && mfma_tflops && fma_tflops, "NULL output");
+    NEGF_REQUIRE(n_mfma >= 0 && n_fma >= 0 && n_mfma + n_fma > 0, "bad chain counts (%d, %d)", n_mfma, n_fma);
+    NEGF_TRY(bind_device(ctx));
+    return issue_probe_f64(ctx, n_mfma, n_fma, ms, mfma_tflops, fma_tflops, (hipStream_t)stream);
+}
+
 // ============================================================== Dyson / energy
 namespace {
 int check_dyson_common(negf_ctx* ctx, const negf_tau_grid_t* tg, int n_b, int sigma, int dtype) {

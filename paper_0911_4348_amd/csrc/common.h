@@ -86,6 +86,8 @@ int s2b_batch_launch(const S2BBatch& plan, hipStream_t st);
 // Sustained rate (TFLOP/s) of the dtype's MFMA shape and the shader clock (GHz)
 // it ran at, from a kernel of independent MFMA chains; synchronises.
 int matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* ghz, hipStream_t st);
+int issue_probe_f64(negf_ctx* ctx, int n_mfma, int n_fma, double* ms, double* tf_mfma, double* tf_fma,
+                    hipStream_t st);
 int s2b_batch_tune(negf_ctx* ctx, int dtype, int batch, const int* n, int n_tau, const int* sigma,
                    const void* const* V, const void* const* G, void* const* Sc, int pair_lim, int* best, double* ms,
                    hipStream_t st);

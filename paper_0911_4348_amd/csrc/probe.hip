@@ -140,7 +140,89 @@ int run(negf_ctx* ctx, int iters, double* tflops, double* ghz, hipStream_t st) {
     return NEGF_OK;
 }
 
+// Float64 issue probe: NM independent chains of the four-block 4x4x4 float64
+// MFMA and NV independent chains of the float64 vector FMA per wave, one
+// instruction of each chain per iteration, register operands only. Comparing
+// the time of a mixed loop with those of its two parts shows whether the two
+// kinds of operation run side by side on a SIMD.
+template <int NM, int NV>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_issue_mix(int iters, double* __restrict__ out) {
+    const int t = threadIdx.x;
+    double acc[NM > 0 ? NM : 1], x[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x[j] = 1.0 + j * 1e-3 + t * 1e-6;
+    const double a = t * 1e-3, b = 1.0 + t * 1e-4, y = 0.999999, z = 1e-7;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int j = 0; j < (NM > NV ? NM : NV); ++j) {
+            if (j < NM) acc[j] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[j], 0, 0, 0);
+            if (j < NV) x[j] = __builtin_fma(x[j], y, z);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) s += acc[j];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s += x[j];
+    out[(long)blockIdx.x * blockDim.x + t] = s;
+}
+
+template <int NM, int NV>
+int issue_run(negf_ctx* ctx, int iters, double* ms, double* tf_mfma, double* tf_fma, hipStream_t st) {
+    int dev = 0, n_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (n_cu <= 0) {
+        set_error("device reports %d compute units", n_cu);
+        return NEGF_ENODEV;
+    }
+    const int blocks = n_cu * kBlocksPerCU;
+    double* out = nullptr;
+    NEGF_TRY(scratch_t(ctx, "probe_out", (size_t)blocks * 64 * kWavesPerBlock, &out));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(hipEventRecord(e0, st));
+        hipLaunchKernelGGL((k_issue_mix<NM, NV>), dim3(blocks), dim3(64 * kWavesPerBlock), 0, st, iters, out);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (rep == 0 || t < best_ms) best_ms = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const double waves = (double)blocks * kWavesPerBlock, sec = best_ms * 1e-3;
+    *ms = best_ms;
+    *tf_mfma = sec > 0 ? waves * iters * NM * Shape<NEGF_F64>::flops / sec * 1e-12 : 0.0;
+    *tf_fma = sec > 0 ? waves * iters * NV * 2.0 * 64 / sec * 1e-12 : 0.0;
+    return NEGF_OK;
+}
+
 }  // namespace
+
+int issue_probe_f64(negf_ctx* ctx, int n_mfma, int n_fma, double* ms, double* tf_mfma, double* tf_fma,
+                    hipStream_t st) {
+    constexpr int it = 20000;
+#define NEGF_ISSUE(NM, NV) \
+    if (n_mfma == NM && n_fma == NV) return issue_run<NM, NV>(ctx, it, ms, tf_mfma, tf_fma, st)
+    NEGF_ISSUE(8, 0);
+    NEGF_ISSUE(0, 8);
+    NEGF_ISSUE(0, 32);
+    NEGF_ISSUE(8, 2);
+    NEGF_ISSUE(8, 4);
+    NEGF_ISSUE(8, 8);
+    NEGF_ISSUE(8, 16);
+    NEGF_ISSUE(8, 32);
+#undef NEGF_ISSUE
+    set_error("issue probe: (%d MFMA, %d FMA chains) is not one of the built combinations", n_mfma, n_fma);
+    return NEGF_EINVAL;
+}
 
 int matrix_rate(negf_ctx* ctx, int dtype, double* tflops, double* ghz, hipStream_t st) {
     switch (dtype) {

@@ -35,3 +35,16 @@ def test_matrix_rate_bounded_by_clock(ctx, dtype):
 def test_matrix_rate_rejects_bad_dtype(ctx):
     with pytest.raises(KeyError):
         negf.matrix_rate(ctx, "f16")
+
+
+def test_issue_probe_runs_and_stays_below_peak(ctx):
+    """negf_f64_issue_probe: every built combination runs and reports rates that the
+    float64 datasheet peak bounds; an unbuilt combination is refused."""
+    for nm, nv in ((8, 0), (0, 8), (8, 8)):
+        ms, tm, tv = negf.f64_issue_probe(ctx, nm, nv)
+        print(f"{nm} MFMA, {nv} FMA chains: {ms:.3f} ms, {tm:.1f} + {tv:.1f} TFLOP/s")
+        assert ms > 0.0
+        assert (tm > 0.0) == (nm > 0) and (tv > 0.0) == (nv > 0)
+        assert tm + tv <= PEAK_AT_2400MHZ["f64"] * 1.05
+    with pytest.raises(negf.NegfError):
+        negf.f64_issue_probe(ctx, 4, 4)

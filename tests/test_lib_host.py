@@ -146,6 +146,17 @@ def test_matrix_rate_rejects_bad_arguments(L):
     assert rc == negf.EINVAL
 
 
+def test_issue_probe_rejects_bad_arguments(L):
+    """negf_f64_issue_probe validates on the host before touching a device."""
+    ms, tm, tv = C.c_double(), C.c_double(), C.c_double()
+    rc = L.negf_f64_issue_probe(None, 8, 0, C.byref(ms), C.byref(tm), C.byref(tv), None)
+    assert rc == negf.EINVAL and b"ctx" in L.negf_last_error()
+    rc = L.negf_f64_issue_probe(C.c_void_p(1), 0, 0, C.byref(ms), C.byref(tm), C.byref(tv), None)
+    assert rc == negf.EINVAL and b"chain counts" in L.negf_last_error()
+    rc = L.negf_f64_issue_probe(C.c_void_p(1), 8, 0, None, C.byref(tm), C.byref(tv), None)
+    assert rc == negf.EINVAL
+
+
 def test_bf16_slice_limit_checked_on_host(L):
     """NEGF_BF16 takes at most 65535 slices; the limit is checked before any device work."""
     fake = C.c_void_p(1)
