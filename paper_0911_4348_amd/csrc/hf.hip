@@ -263,6 +263,48 @@ __global__ __launch_bounds__(256) void k_hf_energy(int n, long stride, const dou
     }
 }
 
+// Pulay (DIIS) error of a Fock matrix F built from rho: E = F rho - rho F,
+// which vanishes at self-consistency (rho is a function of F). With P = F rho,
+// rho F = P^T for symmetric F and rho, so E = P - P^T; grid.y = system.
+__global__ void k_comm_err(int n, long stride, const double* Pb, double* Eb, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double* P = Pb + b * stride;
+    double* E = Eb + b * stride;
+    const long nn = (long)n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        E[e] = P[e] - P[(long)j * n + i];
+    }
+}
+
+// DIIS history [M][B][nn]: dots[b M + k] = <E_slot, E_k> for k < nh; grid (nh, B).
+__global__ __launch_bounds__(256) void k_diis_dots(long nn, int B, int M, const double* Eh, int slot, double* dots,
+                                                   const int* active) {
+    const int k = blockIdx.x, b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double* En = Eh + ((long)slot * B + b) * nn;
+    const double* Ek = Eh + ((long)k * B + b) * nn;
+    __shared__ double red[256 / 64 + 1];
+    double s = 0.0;
+    for (long e = threadIdx.x; e < nn; e += 256) s += En[e] * Ek[e];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) dots[(long)b * M + k] = s;
+}
+
+// F[b] = sum over k < nh of c[b M + k] Fh[k][b]; grid.y = system.
+__global__ void k_diis_combine(long nn, int B, int M, int nh, const double* Fh, const double* c, double* Fb,
+                               const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    double* F = Fb + b * nn;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int k = 0; k < nh; ++k) v += c[(long)b * M + k] * Fh[((long)k * B + b) * nn + e];
+        F[e] = v;
+    }
+}
+
 // g[q][k] = (1 - f_k) e^(-tau_q xi_k) in the form with non-positive exponents
 __global__ void k_g0_table(int n, int n_tau, const double* tau, double beta, const double* eps, double mu,
                            double* g) {
@@ -296,6 +338,50 @@ __global__ void k_transpose(int n, long stride, const double* in, double* out) {
         o[(e % n) * n + e / n] = a[e];
 }
 
+// Pulay coefficients over q history entries (indices idx[0..q), Gram matrix
+// gram[i * M + j] = <E_i, E_j>): minimise |sum c_k E_k| subject to sum c_k = 1,
+// i.e. [G 1; 1^T 0] [c; l] = [0; 1], by Gaussian elimination with partial
+// pivoting on the Gram matrix scaled by its largest diagonal entry. Returns
+// false if the system is singular to working precision.
+bool diis_solve(int q, const int* idx, const double* gram, int M, double* c) {
+    double a[8][9];
+    const int m = q + 1;
+    double scale = 0.0;
+    for (int i = 0; i < q; ++i) scale = std::max(scale, std::fabs(gram[idx[i] * M + idx[i]]));
+    if (!(scale > 0.0) || !std::isfinite(scale)) return false;
+    for (int i = 0; i < q; ++i) {
+        for (int j = 0; j < q; ++j) a[i][j] = gram[idx[i] * M + idx[j]] / scale;
+        a[i][q] = 1.0;
+        a[i][m] = 0.0;
+    }
+    for (int j = 0; j < q; ++j) a[q][j] = 1.0;
+    a[q][q] = 0.0;
+    a[q][m] = 1.0;
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+        if (std::fabs(a[piv][col]) < 1e-14) return false;
+        if (piv != col)
+            for (int k = 0; k <= m; ++k) std::swap(a[piv][k], a[col][k]);
+        for (int r = col + 1; r < m; ++r) {
+            const double f = a[r][col] / a[col][col];
+            for (int k = col; k <= m; ++k) a[r][k] -= f * a[col][k];
+        }
+    }
+    double x[8];
+    for (int r = m - 1; r >= 0; --r) {
+        double v = a[r][m];
+        for (int k = r + 1; k < m; ++k) v -= a[r][k] * x[k];
+        x[r] = v / a[r][r];
+    }
+    for (int i = 0; i < q; ++i) {
+        if (!std::isfinite(x[i])) return false;
+        c[i] = x[i];
+    }
+    return true;
+}
+
 int transpose_batched(const double* in, double* out, int n, int B, hipStream_t st) {
     const long nn = (long)n * n;
     const unsigned g = grid_for(nn) > 256 ? 256 : grid_for(nn);
@@ -326,8 +412,21 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
     NEGF_TRY(scratch_t(ctx, "hf_mu", B, &dmu));
     NEGF_TRY(scratch_t(ctx, "hf_res", 2 * B, &dres));
     NEGF_TRY(scratch_t(ctx, "hf_act", B, &dact));
+    // Pulay (DIIS) extrapolation of the Fock matrix over the last DIIS_M
+    // iterations: same fixed point as the plain iteration, fewer iterations.
+    // A system uses it while its last density change exceeds DIIS_OFF; the
+    // iterations after that are plain, so the returned eigenpairs are those of
+    // h + Sigma0 exactly as in the plain iteration.
+    constexpr int DIIS_M = 6;
+    constexpr double DIIS_OFF = 1e-9;
+    double *Fh, *Eh, *ddots, *dcoef;
+    NEGF_TRY(scratch_t(ctx, "hf_diis_F", (size_t)DIIS_M * nn * B, &Fh));
+    NEGF_TRY(scratch_t(ctx, "hf_diis_E", (size_t)DIIS_M * nn * B, &Eh));
+    NEGF_TRY(scratch_t(ctx, "hf_diis_dots", (size_t)DIIS_M * B, &ddots));
+    NEGF_TRY(scratch_t(ctx, "hf_diis_c", (size_t)DIIS_M * B, &dcoef));
+    std::vector<double> gram((size_t)B * DIIS_M * DIIS_M, 0.0), hdots((size_t)DIIS_M * B), hcoef((size_t)DIIS_M * B);
     std::vector<int> act(B, 1), its(B, max_iter);
-    std::vector<double> E(B, 0.0), E_old(B, INFINITY), hres(2 * B);
+    std::vector<double> E(B, 0.0), E_old(B, INFINITY), hres(2 * B), dlast(B, INFINITY);
     HIP_TRY(hipMemcpyAsync(dact, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
 
     const int npair = (n + 1) / 2;
@@ -375,6 +474,50 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
     for (it = 1; it <= max_iter && n_active > 0; ++it) {
         hipLaunchKernelGGL(k_fock, g2, dim3(256), 0, st, n, nn, T, v, V, rho, sigma, F, Sigma0, dact);
         LAUNCH_CHECK();
+        {
+            // DIIS: store F and its error F rho - rho F in slot (it - 1) mod DIIS_M,
+            // form the new row of each system's Gram matrix, then replace F by the
+            // combination of the stored ones whose error combination is smallest
+            const int slot = (it - 1) % DIIS_M, nh = std::min(it, DIIS_M);
+            double* Fs = Fh + (long)slot * B * nn;
+            double* Es = Eh + (long)slot * B * nn;
+            HIP_TRY(hipMemcpyAsync(Fs, F, sizeof(double) * nn * B, hipMemcpyDeviceToDevice, st));
+            NEGF_TRY(gemm<double>(st, false, false, n, n, n, 1.0, F, n, nn, rho, n, nn, 0.0, nullptr, 0, 0, tmp, n, nn,
+                                  B));
+            hipLaunchKernelGGL(k_comm_err, g2, dim3(256), 0, st, n, nn, tmp, Es, dact);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_diis_dots, dim3(nh, B), dim3(256), 0, st, nn, B, DIIS_M, Eh, slot, ddots, dact);
+            LAUNCH_CHECK();
+            HIP_TRY(hipMemcpyAsync(hdots.data(), ddots, sizeof(double) * DIIS_M * B, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            bool any = false;                          // some system extrapolates
+            for (int b = 0; b < B; ++b) {
+                double* gb = gram.data() + (size_t)b * DIIS_M * DIIS_M;
+                double* cb = hcoef.data() + (size_t)b * DIIS_M;
+                std::fill(cb, cb + DIIS_M, 0.0);
+                cb[slot] = 1.0;
+                if (!act[b]) continue;
+                for (int k = 0; k < nh; ++k) gb[slot * DIIS_M + k] = gb[k * DIIS_M + slot] = hdots[(size_t)b * DIIS_M + k];
+                if (!(dlast[b] > DIIS_OFF)) continue;
+                // the newest q entries; fewer if the Gram system is singular
+                for (int q = nh; q >= 2; --q) {
+                    int idx[DIIS_M];
+                    double cq[DIIS_M];
+                    for (int t = 0; t < q; ++t) idx[t] = (slot - t + DIIS_M) % DIIS_M;
+                    if (diis_solve(q, idx, gb, DIIS_M, cq)) {
+                        cb[slot] = 0.0;
+                        for (int t = 0; t < q; ++t) cb[idx[t]] = cq[t];
+                        any = true;
+                        break;
+                    }
+                }
+            }
+            if (any) {
+                HIP_TRY(hipMemcpyAsync(dcoef, hcoef.data(), sizeof(double) * DIIS_M * B, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_diis_combine, g2, dim3(256), 0, st, nn, B, DIIS_M, nh, Fh, dcoef, F, dact);
+                LAUNCH_CHECK();
+            }
+        }
         HIP_TRY(hipMemcpyAsync(Cp, C, sizeof(double) * nn * B, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(rho_old, rho, sizeof(double) * nn * B, hipMemcpyDeviceToDevice, st));
         NEGF_TRY(eig(F, Cp));
@@ -390,6 +533,7 @@ int hf_run_batched(negf_ctx* ctx, int B, int n, const double* T, const double* v
         if (std::isfinite(d_min)) jac_tol = std::max(1e-15, std::min(1e-8, 1e-4 * d_min));
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
+            dlast[b] = hres[2 * b + 1];
             E[b] = hres[2 * b];
             if (!std::isfinite(E[b])) {
                 set_error("HF energy not finite at iteration %d (system %d)", it, b);
