@@ -35,6 +35,19 @@ def test_scan_recipe():
         assert s.tau_kind == "uniform" and s.M == 1024 and s.beta == 100.0
 
 
+def test_small_scan_recipe():
+    systems = W.config_scan_small()
+    assert len(systems) == 64
+    R = np.array([s.centres[-1] for s in systems])
+    assert R[0] == 1.0 and abs(R[-1] - 3.0) < 1e-12
+    sizes = [n_b(s) for s in systems]
+    assert min(sizes) == 29 and max(sizes) == 69 and sizes == sorted(sizes)
+    for s, r in zip(systems, R):
+        assert abs(s.bounds[-1] - (10.0 + 2.0 * r)) < 1e-12
+        assert len(s.bounds) - 1 == int(round(6 + 4 * (r - 1.0)))
+        assert s.tau_kind == "uniform" and s.M == 1024 and s.beta == 100.0
+
+
 def test_random_potentials_are_seeded():
     a, b = W.random_potential_system(100000), W.random_potential_system(100000)
     assert np.array_equal(a.centres, b.centres) and np.array_equal(a.charges, b.charges)

@@ -164,6 +164,20 @@ def config_scan(n: int = 64, M: int = 1024) -> List[System]:
     return out
 
 
+def config_scan_small(n: int = 64, M: int = 1024) -> List[System]:
+    """The same bond-length scan in short boxes: R uniform in [1, 3], box half-width
+    10 + 2 R, round(6 + 4 (R - 1)) equal elements of 6 GLL points (n_b 29..69),
+    beta = 100, uniform tau grid. Many small systems, none of which fills the GPU
+    alone: the case in which batching them matters."""
+    out = []
+    for k in range(n):
+        R = scan_R(k, n)
+        n_e = int(round(6 + 4 * (R - 1.0)))
+        out.append(h3p_1d(R=R, half_width=10.0 + 2.0 * R, n_e=n_e, n_g=5, beta=100.0,
+                          tau_kind="uniform", M=M))
+    return out
+
+
 def random_potential_system(seed: int, base: System | None = None) -> System:
     """Two electrons in a seeded random soft-Coulomb potential: 1-3 centres,
     charges in [1, 2], positions in [-3, 3]; grid and tau grid of ``base``
