@@ -241,12 +241,15 @@ int negf_sigma2b_tune(negf_ctx* ctx, int n_b, int n_tau, int sigma, const void* 
  * doubles, np = n_b rounded up to 16): 11 with 8 values of i and k-panels of
  * 16 (one workgroup per compute unit; n_b <= 240), 12 with 4 values of i and
  * k-panels of 4 (75 KB of LDS at n_b <= 208, two workgroups per compute unit).
+ * With an odd n_tau, 11 and 12 split the middle slice (tau = beta/2) over up to
+ * 8 parts of its rows l and add the parts in a second kernel; the parts take
+ * 2 * 8 * ceil(n_b/IB) * IB * np more doubles of context scratch (IB = 8 or 4).
  * The float64 matrix-core tiles (0-5, 11, 12) run on the four-block 4x4x4
  * float64 MFMA shape. */
 int negf_sigma2b_set_config(negf_ctx* ctx, int n_b, int dtype, int cfg);
 
-/* negf_matrix_rate, a measurement helper outside the method, is declared in
- * negf_measure.h. */
+/* negf_matrix_rate and negf_f64_issue_probe, measurement helpers outside the
+ * method, are declared in negf_measure.h. */
 
 /* Sigma-2B (as negf_sigma2b) for `batch` systems of any sizes n_b[b] on one
  * tau grid of n_tau points, in a single persistent kernel launch: work items
