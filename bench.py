@@ -36,9 +36,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # HBM bytes per k_sigma2b dispatch (float64, n_b = 199, 1025 slices) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (profiles/k_sigma2b_f64_nb199_ntau1025.md), per tile
 # configuration; valid only for the kernel source they were measured on (hash prefix below).
-TRAFFIC_SRC_SHA256 = "f6add80b3bd24cc9"
-TRAFFIC_F64_NB199 = {0: 656775671, 1: 657093108, 2: 656921231, 3: 657573752, 4: 657644871, 5: 1953808911,
-                     8: 663828924, 9: 664908269, 10: 663835326, 11: 871589318, 12: 683065387}
+TRAFFIC_SRC_SHA256 = "d3f01f6ddc245145"
+TRAFFIC_F64_NB199 = {0: 656768626, 1: 657117682, 2: 656913899, 3: 657618170, 4: 657664952, 5: 1952635368,
+                     8: 663099488, 9: 664681557, 10: 663261610, 11: 871530902, 12: 683045701}
 
 
 def measured_traffic(dtype, n, n_tau, cfg):

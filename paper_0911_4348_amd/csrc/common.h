@@ -108,6 +108,10 @@ template <class T>
 int sigma2b_run(negf_ctx* ctx, int n_b, int n_tau, int sigma, const T* V, const T* G,
                 T* Sc, bool bf16, hipStream_t st);
 int sigma2b_set_cfg(negf_ctx* ctx, int dtype, int n_b, int cfg);
+// Float64 Sigma-2B of one system in the tuned configuration, else the fastest
+// one measured at n_b = 199 where it fits (the direct-to-LDS tile).
+int sigma2b_run_f64_single(negf_ctx* ctx, int n_b, int n_tau, int sigma, const double* V, const double* G,
+                           double* Sc, hipStream_t st);
 // Allocation-free form (float64 / float32): the float32 slice exponents go to a
 // fixed per-device array whose address s2b_noalloc_init (device current) records.
 int s2b_noalloc_init(int device);

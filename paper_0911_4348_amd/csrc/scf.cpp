@@ -11,7 +11,9 @@
 //
 // Batch execution: one iteration of all unfinished systems is two stream
 // segments, (a) Sigma_2B of every system in one persistent kernel launch per
-// arithmetic mode plus every energy, (b) every Dyson step. The energies are
+// arithmetic mode plus every energy, (b) every Dyson step. A batch of one system
+// runs its float64 Sigma_2B through the single-system tiles instead (the
+// direct-to-LDS tile where it fits), which the persistent kernel does not have. The energies are
 // read back between them (the only host synchronisation per iteration). Each
 // segment is recorded once as a HIP graph and replayed while the set of
 // unfinished systems does not change; a new set is first run directly (it may
@@ -358,6 +360,8 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
         // tile autotuner for each arithmetic mode over the whole batch (first 16 slice pairs)
         for (int pass = 0; pass < (low ? 2 : 1); ++pass) {
             const int dt = pass == 0 ? o->dtype : NEGF_F64;
+            // a single system's float64 Sigma-2B does not use the persistent kernel
+            if (batch == 1 && dt == NEGF_F64) continue;
             std::vector<int> n(batch), sg(batch);
             std::vector<const void*> Vp(batch), Gp(batch);
             std::vector<void*> Sp(batch);
@@ -419,7 +423,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
                                          Sp.data(), 0, pl, st);
             };
             NEGF_TRY(prep(act_lo, o->dtype, "lo", &plan_lo));
-            NEGF_TRY(prep(act_hi, NEGF_F64, "hi", &plan_hi));
+            if (batch > 1) NEGF_TRY(prep(act_hi, NEGF_F64, "hi", &plan_hi));
             plan_key = keyS;
             gS.drop();
             gD.drop();
@@ -429,7 +433,15 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
         // (a) Sigma_2B of every unfinished system, then every energy
         NEGF_TRY(run_segment(gS, keyS, graphs, gD, st, [&]() -> int {
             if (!act_lo.empty()) NEGF_TRY(s2b_batch_launch(plan_lo, st));
-            if (!act_hi.empty()) NEGF_TRY(s2b_batch_launch(plan_hi, st));
+            if (!act_hi.empty()) {
+                if (batch == 1) {
+                    // one system: the float64 tile of negf_sigma2b (direct-to-LDS where it fits)
+                    const Sys& y = S[act_hi[0]];
+                    NEGF_TRY(sigma2b_run_f64_single(ctx, y.n, n_tau, systems[y.b].sigma, y.V, y.G, y.Sc, st));
+                } else {
+                    NEGF_TRY(s2b_batch_launch(plan_hi, st));
+                }
+            }
             for (int r : act_lo) {
                 const Sys& y = S[r];
                 NEGF_TRY(energy_launch<float>(ctx, &tg, y.n, systems[y.b].sigma, y.h, y.V, y.Gf, y.Scf,

@@ -1546,6 +1546,19 @@ int sigma2b_cfg(negf_ctx* ctx, int n, int n_tau, int sigma, const T* V, const T*
     return launch<MODE_F32>(ctx, n, n_tau, sigma, (const float*)V, (const float*)G, (float*)Sc, cfg, st, ex_fixed);
 }
 
+// Float64 Sigma-2B of one system: the configuration tuned for (float64, n_b) in
+// this context, else the direct-to-LDS tile with 8 values of i (configuration
+// 11) where its LDS fits n_b, else the default. Stream-ordered; after its first
+// call for a size (scratch, kernel attribute) it may be captured in a graph.
+int sigma2b_run_f64_single(negf_ctx* ctx, int n, int n_tau, int sigma, const double* V, const double* G, double* Sc,
+                           hipStream_t st) {
+    auto it = ctx->filled.find(tune_key(MODE_F64, n));
+    int cfg = default_cfg(MODE_F64, n);
+    if (it != ctx->filled.end()) cfg = it->second;
+    else if (dma::Layout<8, 13, 16>::bytes((n + 15) & ~15) <= 160 * 1024) cfg = 11;
+    return sigma2b_cfg<double>(ctx, n, n_tau, sigma, V, G, Sc, false, cfg, st);
+}
+
 // ---------------------------------------------------------------- allocation-free entry
 // The per-slice exponents of the float32 mode live in a fixed device array for
 // callers that cannot allocate (one copy per GPU, kept until the process ends).
