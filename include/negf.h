@@ -410,9 +410,9 @@ int negf_scf(negf_ctx* ctx, const negf_system_t* sys, const negf_opts_t* opts,
  * graphs and replayed while the set of unfinished systems is unchanged. Each
  * system stops by its own rule, so its result equals negf_scf on it alone (to
  * rounding: the tile configuration may differ). A batch of one system (what
- * negf_scf runs) evaluates its float64 Sigma_2B with negf_sigma2b's tiles
- * instead: the configuration tuned for (NEGF_F64, n_b) in the context, else
- * configuration 11 where it fits n_b (the autotuner then skips float64).
+ * negf_scf runs) with n_b <= 240 evaluates its float64 Sigma_2B with
+ * negf_sigma2b's tiles instead: the configuration tuned for (NEGF_F64, n_b) in
+ * the context, else configuration 11 (the autotuner then skips float64).
  * systems (host, batch). G_guess, G_out (host arrays of batch device pointers,
  * each float64 [n_tau][n_b][n_b]; the arrays and their entries nullable).
  * E_out, N_out, iters, hf_E, hf_mu, log_n (host, batch entries, nullable);

@@ -12,8 +12,8 @@
 // Batch execution: one iteration of all unfinished systems is two stream
 // segments, (a) Sigma_2B of every system in one persistent kernel launch per
 // arithmetic mode plus every energy, (b) every Dyson step. A batch of one system
-// runs its float64 Sigma_2B through the single-system tiles instead (the
-// direct-to-LDS tile where it fits), which the persistent kernel does not have. The energies are
+// with n_b <= 240 runs its float64 Sigma_2B through the single-system tiles
+// instead (the direct-to-LDS tile), which the persistent kernel does not have. The energies are
 // read back between them (the only host synchronisation per iteration). Each
 // segment is recorded once as a HIP graph and replayed while the set of
 // unfinished systems does not change; a new set is first run directly (it may
@@ -356,12 +356,16 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
         n_hf_fail += !y.hf_ok;
     }
     if (n_hf_fail) set_error("HF not converged for %d system(s); those were not iterated", n_hf_fail);
+    // One system whose direct-to-LDS float64 tile fits its LDS (n_b <= 240, the
+    // limit of Sigma-2B configuration 11) runs its float64 Sigma_2B through the
+    // single-system tiles; everything else through the persistent kernel.
+    const bool single_f64 = batch == 1 && S[0].n <= 240;
     if (o->tune) {
         // tile autotuner for each arithmetic mode over the whole batch (first 16 slice pairs)
         for (int pass = 0; pass < (low ? 2 : 1); ++pass) {
             const int dt = pass == 0 ? o->dtype : NEGF_F64;
             // a single system's float64 Sigma-2B does not use the persistent kernel
-            if (batch == 1 && dt == NEGF_F64) continue;
+            if (single_f64 && dt == NEGF_F64) continue;
             std::vector<int> n(batch), sg(batch);
             std::vector<const void*> Vp(batch), Gp(batch);
             std::vector<void*> Sp(batch);
@@ -423,7 +427,7 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
                                          Sp.data(), 0, pl, st);
             };
             NEGF_TRY(prep(act_lo, o->dtype, "lo", &plan_lo));
-            if (batch > 1) NEGF_TRY(prep(act_hi, NEGF_F64, "hi", &plan_hi));
+            if (!single_f64) NEGF_TRY(prep(act_hi, NEGF_F64, "hi", &plan_hi));
             plan_key = keyS;
             gS.drop();
             gD.drop();
@@ -434,8 +438,8 @@ extern "C" int negf_scf_batched(negf_ctx* ctx, int batch, const negf_system_t* s
         NEGF_TRY(run_segment(gS, keyS, graphs, gD, st, [&]() -> int {
             if (!act_lo.empty()) NEGF_TRY(s2b_batch_launch(plan_lo, st));
             if (!act_hi.empty()) {
-                if (batch == 1) {
-                    // one system: the float64 tile of negf_sigma2b (direct-to-LDS where it fits)
+                if (single_f64) {
+                    // one system: the float64 tile of negf_sigma2b (direct-to-LDS)
                     const Sys& y = S[act_hi[0]];
                     NEGF_TRY(sigma2b_run_f64_single(ctx, y.n, n_tau, systems[y.b].sigma, y.V, y.G, y.Sc, st));
                 } else {
